@@ -1,0 +1,121 @@
+/*
+ * moma.h - C ABI of the MI355X (gfx950) multi-word modular arithmetic library.
+ *
+ * The library computes, exactly, over a prime field Z_q whose elements are
+ * split into 32-bit machine words ("limbs"):
+ *   - the ring operations of the paper's Section 2.1 applied elementwise to
+ *     vectors (vadd, vsub, vmul) and axpy y = a*x + y (Section 2.3);
+ *   - the forward number theoretic transform of Eq. (ntt),
+ *     y(k) = sum_j x(j) w^{jk} mod q, and its inverse
+ *     x(j) = n^{-1} sum_k y(k) w^{-jk} mod q.
+ * Every output is the unique canonical residue in [0, q).
+ *
+ * Data layout
+ *   Scalars (q, omega, alpha) are HOST pointers to `limbs` little-endian
+ *   32-bit words (word 0 least significant).  The paper writes digits most
+ *   significant first (Eq. (def_mp)); only the storage order differs.
+ *   Vectors are DEVICE pointers in limb-planar layout: word j of element i is
+ *   at index j*n + i (so a wavefront reads 64 consecutive words per limb).
+ *   Inputs must be canonical (each element < q); words of limbs above the
+ *   top limb of q must therefore be zero.  Non-canonical inputs give
+ *   undefined (but memory-safe) results.
+ *
+ * Preconditions checked on the host before anything is enqueued
+ *   2 <= limbs <= 32; q odd, q >= 3, bitlen(q) <= 32*limbs - 4 (the paper's
+ *   moduli are four bits short of the class width, Section 5.2);
+ *   n a power of two, 2 <= n <= 2^26 (BLAS: any n >= 0);
+ *   omega of multiplicative order exactly n (omega^{n/2} == q - 1), which
+ *   also implies n | q - 1 for prime q.  Primality of q is the caller's
+ *   contract.
+ *
+ * Ownership and concurrency
+ *   The caller owns device buffers and streams.  The library owns cached
+ *   plans (twiddle tables, constants, scratch) until moma_shutdown().
+ *   In-place operation is allowed (d_out == d_in, d_out == d_a/d_b,
+ *   d_out == d_y); partial overlap is undefined.  Work is enqueued on
+ *   `stream` (a hipStream_t passed as void*; NULL is the default stream) and
+ *   returns without synchronising.  Plan creation may allocate device memory
+ *   and synchronise once.  The plan cache is thread safe.
+ *
+ * Errors
+ *   Functions return MOMA_OK (0) or a negative code; moma_strerror() names
+ *   it and moma_last_error_detail() gives the last failure's text.
+ */
+#ifndef MOMA_H
+#define MOMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MOMA_OK = 0,
+  MOMA_E_ARG = -1,         /* null pointer, bad size, bad limb count      */
+  MOMA_E_MODULUS = -2,     /* q even, too small, or too wide for `limbs`  */
+  MOMA_E_ROOT = -3,        /* omega does not have order exactly n         */
+  MOMA_E_NOMEM = -4,       /* device allocation failed                    */
+  MOMA_E_HIP = -5,         /* a HIP runtime call failed                   */
+  MOMA_E_UNSUPPORTED = -6  /* valid request this build cannot run          */
+};
+
+#define MOMA_MIN_LIMBS 2
+#define MOMA_MAX_LIMBS 32
+#define MOMA_MAX_LOG_N 26
+
+/* Name of an error code (static string). */
+const char* moma_strerror(int code);
+/* Text describing the most recent failure on the calling thread. */
+const char* moma_last_error_detail(void);
+/* Library version string. */
+const char* moma_version(void);
+
+/*
+ * Elementwise modular BLAS (paper Section 2.3; ring operations of Section 2.1).
+ *   moma_vadd: out_i = (a_i + b_i) mod q
+ *   moma_vsub: out_i = (a_i - b_i) mod q
+ *   moma_vmul: out_i = (a_i * b_i) mod q      (Barrett reduction, Eq. (barrett))
+ *   moma_axpy: out_i = (alpha * x_i + y_i) mod q   (Montgomery multiply by alpha)
+ * n is the element count (0 is a no-op).  Device arrays are limb-planar with
+ * `limbs` planes of n words.  alpha is a host scalar in [0, q).
+ */
+int moma_vadd(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a, const uint32_t* d_b,
+              uint32_t* d_out, void* stream);
+int moma_vsub(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a, const uint32_t* d_b,
+              uint32_t* d_out, void* stream);
+int moma_vmul(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a, const uint32_t* d_b,
+              uint32_t* d_out, void* stream);
+int moma_axpy(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* alpha, const uint32_t* d_x,
+              const uint32_t* d_y, uint32_t* d_out, void* stream);
+
+/*
+ * Number theoretic transform, Eq. (ntt): natural order in, natural order out.
+ *   moma_ntt_fwd: d_out[k] = sum_j d_in[j] * omega^{jk} mod q
+ *   moma_ntt_inv: d_out[j] = n^{-1} sum_k d_in[k] * omega^{-jk} mod q
+ * `omega` is the FORWARD primitive n-th root in both calls; the inverse uses
+ * omega^{-1} and n^{-1} itself.  A butterfly is one modular add, one modular
+ * subtract and one modular multiply (Section 5.3); a transform performs
+ * (n/2) log2 n of them.  The first call for a given (q, omega, n, limbs)
+ * builds a plan (twiddle tables on the device) and synchronises once.
+ */
+int moma_ntt_fwd(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const uint32_t* d_in,
+                 uint32_t* d_out, void* stream);
+int moma_ntt_inv(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const uint32_t* d_in,
+                 uint32_t* d_out, void* stream);
+
+/*
+ * Build (or look up) the plan for (q, omega, n, limbs) without running a
+ * transform, so timed loops exclude plan creation.  Returns MOMA_OK or an
+ * error code for invalid parameters.
+ */
+int moma_ntt_prepare(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs);
+
+/* Free every cached plan and device table.  Safe to call more than once. */
+void moma_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOMA_H */

@@ -22,6 +22,7 @@ Python's built-in ``pow`` is used for the number-theoretic parameter choice
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -50,15 +51,47 @@ def stream_key(*ids: int) -> int:
     return s
 
 
+def _sm64_chunk(key: np.uint64, idx: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = key + (idx + np.uint64(1)) * np.uint64(GAMMA)
+        z ^= z >> np.uint64(30)
+        z *= np.uint64(0xBF58476D1CE4E5B9)
+        z ^= z >> np.uint64(27)
+        z *= np.uint64(0x94D049BB133111EB)
+        z ^= z >> np.uint64(31)
+    return z
+
+
+_POOL = None
+
+
+def _pool():
+    global _POOL
+    if _POOL is None:
+        from concurrent.futures import ThreadPoolExecutor
+        _POOL = ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1)))
+    return _POOL
+
+
+def splitmix64_at(key: int, idx: np.ndarray) -> np.ndarray:
+    """Outputs number idx (0-based, any uint64 array) of the stream with this key."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint64).reshape(-1)
+    k = np.uint64(key)
+    chunk = 1 << 20
+    if idx.size <= chunk:
+        return _sm64_chunk(k, idx)
+    out = np.empty_like(idx)
+    parts = [(i, min(i + chunk, idx.size)) for i in range(0, idx.size, chunk)]
+
+    def run(p):
+        out[p[0]:p[1]] = _sm64_chunk(k, idx[p[0]:p[1]])
+    list(_pool().map(run, parts))
+    return out
+
+
 def splitmix64(key: int, start: int, count: int) -> np.ndarray:
     """Outputs start .. start+count-1 of the SplitMix64 stream with this key (uint64)."""
-    idx = np.arange(start + 1, start + 1 + count, dtype=np.uint64)
-    with np.errstate(over="ignore"):
-        z = np.uint64(key) + idx * np.uint64(GAMMA)
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        z = z ^ (z >> np.uint64(31))
-    return z
+    return splitmix64_at(key, np.arange(start, start + count, dtype=np.uint64))
 
 
 def splitmix64_scalar(key: int, i: int) -> int:
@@ -203,9 +236,10 @@ def residues(field: Field, n: int, L: int, *ids: int) -> np.ndarray:
     """n uniform residues in [0, q) as (n, L) uint32, element-major.
 
     Element i, attempt t takes 32-bit words from the stream (ids..., t): word j
-    is the low (j even) or high (j odd) half of output i*ceil(L/2) + j//2.  The
-    top used limb is masked to the bit length of q, limbs above it are zero,
-    and attempts >= q are redrawn with t + 1.
+    is the low (j even) or high (j odd) half of output i*ceil(Lq/2) + j//2,
+    where Lq is the number of limbs of q.  The top limb of q is masked to the
+    bit length of q, limbs above it are zero, and attempts >= q are redrawn
+    with t + 1.
     """
     if n == 0:
         return np.zeros((0, L), dtype=np.uint32)
@@ -216,26 +250,34 @@ def residues(field: Field, n: int, L: int, *ids: int) -> np.ndarray:
     ql = int_to_limbs(q, L)
     top_bits = q.bit_length() - 32 * (Lq - 1)
     top_mask = np.uint32((1 << top_bits) - 1) if top_bits < 32 else np.uint32(0xFFFFFFFF)
-    out = np.zeros((n, L), dtype=np.uint32)
-    todo = np.arange(n, dtype=np.int64)
     half = (Lq + 1) // 2
-    t = 0
-    while todo.size:
+
+    def draw(t, rows):
         key = stream_key(*ids, t)
-        # draw the whole index range once, then gather rows that are still open
-        raw = splitmix64(key, 0, n * half).reshape(n, half)[todo]
-        words = np.empty((todo.size, 2 * half), dtype=np.uint32)
-        words[:, 0::2] = (raw & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-        words[:, 1::2] = (raw >> np.uint64(32)).astype(np.uint32)
-        cand = np.zeros((todo.size, L), dtype=np.uint32)
+        if rows is None:
+            raw = splitmix64(key, 0, n * half)
+            m = n
+        else:
+            idx = rows.astype(np.uint64)[:, None] * np.uint64(half) + np.arange(half, dtype=np.uint64)[None, :]
+            raw = splitmix64_at(key, idx)
+            m = rows.size
+        words = raw.view(np.uint32).reshape(m, 2 * half)   # little-endian: low half first
+        cand = np.zeros((m, L), dtype=np.uint32)
         cand[:, :Lq] = words[:, :Lq]
         cand[:, Lq - 1] &= top_mask
-        lt = np.zeros(todo.size, dtype=bool)
-        eq = np.ones(todo.size, dtype=bool)
-        for j in range(L - 1, -1, -1):
-            lt |= eq & (cand[:, j] < ql[j])
-            eq &= cand[:, j] == ql[j]
-        ok = lt
+        lt = np.zeros(m, dtype=bool)
+        eq = np.ones(m, dtype=bool)
+        for j in range(Lq - 1, -1, -1):
+            col = cand[:, j]
+            lt |= eq & (col < ql[j])
+            eq &= col == ql[j]
+        return cand, lt
+
+    out, ok = draw(0, None)
+    todo = np.flatnonzero(~ok)
+    t = 1
+    while todo.size:
+        cand, ok = draw(t, todo)
         out[todo[ok]] = cand[ok]
         todo = todo[~ok]
         t += 1

@@ -1,0 +1,191 @@
+"""Python binding of the MoMA library for MI355X (gfx950).
+
+Argument marshalling only: every step runs in the HIP kernels of libmoma.so
+through the C ABI declared in include/moma.h.  PyTorch supplies device memory
+and streams.  Importing this package fails loudly when libmoma.so is missing;
+there is no CPU fallback.
+
+Vectors are torch tensors on the GPU of shape (limbs, n) holding 32-bit words
+(dtype torch.int32 or torch.uint32), limb-planar: row j is limb j (least
+significant first) of every element.  Scalars q, omega and alpha are Python
+ints.  All functions enqueue on the current torch stream unless `stream` is
+given, and return the output tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmoma.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -m paper_2501_07535_amd.build, or __graft_entry__.build())")
+
+# torch ships its own HIP runtime with the same soname (libamdhip64.so.7).
+# Loading torch first makes libmoma.so bind to that copy, so tensors, streams
+# and our kernels share one runtime; a second runtime instance in the process
+# would see no device.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    try:
+        maps = open("/proc/self/maps").read().splitlines()
+    except OSError:
+        return []
+    return sorted({ln.split()[-1] for ln in maps if "libamdhip64" in ln})
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError(f"two HIP runtimes are loaded ({_hip_runtimes()}); import torch before loading libmoma.so")
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_vp = ctypes.c_void_p
+
+for _name in ("moma_vadd", "moma_vsub", "moma_vmul"):
+    getattr(_lib, _name).argtypes = [_u32p, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp, _vp]
+    getattr(_lib, _name).restype = ctypes.c_int
+_lib.moma_axpy.argtypes = [_u32p, ctypes.c_uint32, ctypes.c_uint64, _u32p, _vp, _vp, _vp, _vp]
+_lib.moma_axpy.restype = ctypes.c_int
+for _name in ("moma_ntt_fwd", "moma_ntt_inv"):
+    getattr(_lib, _name).argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
+    getattr(_lib, _name).restype = ctypes.c_int
+_lib.moma_ntt_prepare.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32]
+_lib.moma_ntt_prepare.restype = ctypes.c_int
+_lib.moma_strerror.argtypes = [ctypes.c_int]
+_lib.moma_strerror.restype = ctypes.c_char_p
+_lib.moma_last_error_detail.restype = ctypes.c_char_p
+_lib.moma_version.restype = ctypes.c_char_p
+_lib.moma_shutdown.restype = None
+
+MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
+            "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_prepare", "moma_shutdown")
+
+
+class MomaError(RuntimeError):
+    def __init__(self, code: int):
+        self.code = code
+        super().__init__(f"{_lib.moma_strerror(code).decode()}: {_lib.moma_last_error_detail().decode()}")
+
+
+def _check(rc: int):
+    if rc != MOMA_OK:
+        raise MomaError(rc)
+
+
+def library():
+    """The loaded ctypes library (for callers that want the raw C ABI)."""
+    return _lib
+
+
+def version() -> str:
+    return _lib.moma_version().decode()
+
+
+def _words(v: int, limbs: int):
+    if v < 0 or v >> (32 * limbs):
+        raise ValueError(f"value does not fit in {limbs} limbs")
+    arr = (ctypes.c_uint32 * limbs)(*[(v >> (32 * j)) & 0xFFFFFFFF for j in range(limbs)])
+    return arr
+
+
+def _dev(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise TypeError(f"{name} must hold 32-bit words (int32 or uint32)")
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous (limbs, n) tensor")
+    return t
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _out(like, out):
+    import torch
+    if out is None:
+        return torch.empty_like(like)
+    _dev(out, "out")
+    if out.shape != like.shape:
+        raise ValueError("out has the wrong shape")
+    return out
+
+
+def _binop(fn, a, b, q, out, stream):
+    _dev(a, "a"); _dev(b, "b")
+    if a.shape != b.shape:
+        raise ValueError("a and b must have the same shape")
+    limbs, n = a.shape
+    out = _out(a, out)
+    _check(fn(_words(q, limbs), limbs, n, a.data_ptr(), b.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def vadd(a, b, q: int, out=None, stream=None):
+    """out = (a + b) mod q elementwise."""
+    return _binop(_lib.moma_vadd, a, b, q, out, stream)
+
+
+def vsub(a, b, q: int, out=None, stream=None):
+    """out = (a - b) mod q elementwise."""
+    return _binop(_lib.moma_vsub, a, b, q, out, stream)
+
+
+def vmul(a, b, q: int, out=None, stream=None):
+    """out = (a * b) mod q elementwise."""
+    return _binop(_lib.moma_vmul, a, b, q, out, stream)
+
+
+def axpy(alpha: int, x, y, q: int, out=None, stream=None):
+    """out = (alpha * x + y) mod q elementwise."""
+    _dev(x, "x"); _dev(y, "y")
+    if x.shape != y.shape:
+        raise ValueError("x and y must have the same shape")
+    limbs, n = x.shape
+    out = _out(x, out)
+    _check(_lib.moma_axpy(_words(q, limbs), limbs, n, _words(alpha, limbs), x.data_ptr(), y.data_ptr(),
+                          out.data_ptr(), _stream(stream)))
+    return out
+
+
+def ntt_fwd(x, q: int, omega: int, out=None, stream=None):
+    """Forward NTT y_k = sum_j x_j omega^{jk} mod q, natural order in and out."""
+    _dev(x, "x")
+    limbs, n = x.shape
+    out = _out(x, out)
+    _check(_lib.moma_ntt_fwd(_words(q, limbs), _words(omega, limbs), n, limbs, x.data_ptr(), out.data_ptr(),
+                             _stream(stream)))
+    return out
+
+
+def ntt_inv(y, q: int, omega: int, out=None, stream=None):
+    """Inverse NTT x_j = n^-1 sum_k y_k omega^{-jk} mod q; omega is the forward root."""
+    _dev(y, "y")
+    limbs, n = y.shape
+    out = _out(y, out)
+    _check(_lib.moma_ntt_inv(_words(q, limbs), _words(omega, limbs), n, limbs, y.data_ptr(), out.data_ptr(),
+                             _stream(stream)))
+    return out
+
+
+def ntt_prepare(q: int, omega: int, n: int, limbs: int):
+    """Build the plan (twiddle tables) for (q, omega, n, limbs) ahead of timed calls."""
+    _check(_lib.moma_ntt_prepare(_words(q, limbs), _words(omega, limbs), n, limbs))
+
+
+def shutdown():
+    _lib.moma_shutdown()

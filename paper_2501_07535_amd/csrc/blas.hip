@@ -1,0 +1,100 @@
+// blas.hip - elementwise modular BLAS kernels (paper Section 2.3 / Section 5.2).
+//
+// One lane per element, limb-planar layout: a wavefront's load of limb j is 64
+// consecutive words (256 bytes), so every access is fully coalesced.  vadd and
+// vsub are HBM-bound (3 * 4L bytes per element against ~3L VALU ops); vmul and
+// axpy carry an L-limb modular multiply per element.
+#include "common.hpp"
+#include "limb.hpp"
+
+namespace moma {
+
+template <int L>
+struct BlasC {
+  u32 q[L];
+  u32 qinv;
+  BarrettC<L> bc;
+  u32 alpha_m[L];
+};
+
+template <int L, int OP>
+__global__ __launch_bounds__(256) void blas_kernel(const u32* __restrict__ pa, const u32* __restrict__ pb,
+                                                   u32* __restrict__ pout, u64 n, BlasC<L> c) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  u32 a[L], b[L], r[L];
+#pragma unroll
+  for (int j = 0; j < L; j++) {
+    a[j] = pa[j * n + i];
+    b[j] = pb[j * n + i];
+  }
+  if (OP == OP_VADD) {
+    mod_add<L>(r, a, b, c.q);
+  } else if (OP == OP_VSUB) {
+    mod_sub<L>(r, a, b, c.q);
+  } else if (OP == OP_VMUL) {
+    barrett_mul<L>(r, a, b, c.bc);
+  } else {
+    u32 t[L];
+    mont_mul<L>(t, a, c.alpha_m, c.q, c.qinv);  // alpha * x
+    mod_add<L>(r, t, b, c.q);                   // + y
+  }
+#pragma unroll
+  for (int j = 0; j < L; j++) pout[j * n + i] = r[j];
+}
+
+// mont_mul takes its second operand from VGPRs; alpha is uniform, so keep a
+// copy per lane (cheap: L moves per element).
+template <int L, int OP>
+static int launch_blas_L(const FieldRaw& f, const BlasArgs& a, hipStream_t s) {
+  BlasC<L> c;
+  for (int j = 0; j < L; j++) {
+    c.q[j] = f.q[j];
+    c.bc.qn[j] = f.qn[j];
+    c.bc.mu[j] = f.mu[j];
+    c.alpha_m[j] = a.alpha_m[j];
+  }
+  c.qinv = f.qinv;
+  c.bc.d = f.d;
+  const unsigned T = 256;
+  u64 blocks = (a.n + T - 1) / T;
+  hipLaunchKernelGGL((blas_kernel<L, OP>), dim3((unsigned)blocks), dim3(T), 0, s, a.a, a.b, a.out, a.n, c);
+  return (int)hipGetLastError();
+}
+
+template <int L>
+static int launch_blas_op(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s) {
+  switch (op) {
+    case OP_VADD: return launch_blas_L<L, OP_VADD>(f, a, s);
+    case OP_VSUB: return launch_blas_L<L, OP_VSUB>(f, a, s);
+    case OP_VMUL: return launch_blas_L<L, OP_VMUL>(f, a, s);
+    case OP_AXPY: return launch_blas_L<L, OP_AXPY>(f, a, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s) {
+  if (a.n == 0) return 0;
+  switch (f.L) {
+#define CASE(LL) \
+  case LL: return launch_blas_op<LL>(op, f, a, s);
+    MOMA_FOR_EACH_L(CASE)
+#undef CASE
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+__global__ __launch_bounds__(256) void zero_planes_kernel(u32* out, u64 n, int from, int to) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = from; j < to; j++) out[(u64)j * n + i] = 0;
+}
+
+int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, hipStream_t s) {
+  if (n == 0 || from_plane >= to_plane) return 0;
+  u64 blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(zero_planes_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out, n, from_plane, to_plane);
+  return (int)hipGetLastError();
+}
+
+}  // namespace moma

@@ -1,0 +1,406 @@
+// capi.cpp - host runtime behind include/moma.h: argument validation, per-modulus
+// constants, the transform plan cache (twiddle tables, pass schedule, scratch)
+// and the extern "C" entry points.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/moma.h"
+#include "common.hpp"
+#include "hostbig.hpp"
+
+namespace moma {
+
+static thread_local std::string g_detail;
+
+int set_error(int code, const std::string& detail) {
+  g_detail = detail;
+  return code;
+}
+
+static int hip_fail(int e, const char* what) {
+  if (e == 0) return MOMA_OK;
+  return set_error(MOMA_E_HIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e));
+}
+
+// ------------------------------------------------------------------ fields
+
+struct FieldEntry {
+  FieldRaw f;
+  HBig Q, one_m;
+  // last axpy scalar, cached with its Montgomery form
+  std::vector<uint32_t> alpha_key;
+  std::vector<uint32_t> alpha_m;
+};
+
+static std::mutex g_mu;
+static std::map<std::vector<uint32_t>, std::shared_ptr<FieldEntry>> g_fields;
+
+static int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* out) {
+  if (!q) return set_error(MOMA_E_ARG, "q is NULL");
+  if (limbs < MOMA_MIN_LIMBS || limbs > MOMA_MAX_LIMBS)
+    return set_error(MOMA_E_ARG, "limbs must be in [2, 32], got " + std::to_string(limbs));
+  std::vector<uint32_t> key(q, q + limbs);
+  key.push_back(limbs);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_fields.find(key);
+    if (it != g_fields.end()) {
+      *out = it->second;
+      return MOMA_OK;
+    }
+  }
+  auto fe = std::make_shared<FieldEntry>();
+  HBig Q = HBig::from_limbs(q, (int)limbs);
+  if (!Q.is_odd() || HBig::cmp(Q, HBig(3)) < 0) return set_error(MOMA_E_MODULUS, "q must be odd and >= 3");
+  int M = Q.bitlen();
+  if (M > 32 * (int)limbs - 4)
+    return set_error(MOMA_E_MODULUS, "bitlen(q) = " + std::to_string(M) + " exceeds 32*limbs-4 = " +
+                                         std::to_string(32 * limbs - 4));
+  FieldRaw& f = fe->f;
+  memset(&f, 0, sizeof(f));
+  f.L = (M + 4 + 31) / 32;
+  f.Ls = (int)limbs;
+  Q.to_limbs(f.q, kMaxLimbs);
+  f.qinv = neg_inv32(f.q[0]);
+  HBig one_m = HBig::mod(HBig::pow2(32 * f.L), Q);
+  one_m.to_limbs(f.one_m, kMaxLimbs);
+  int Mn = 32 * f.L - 4;
+  f.d = (uint32_t)(Mn - M);
+  HBig qn = HBig::shl(Q, (int)f.d);
+  qn.to_limbs(f.qn, kMaxLimbs);
+  HBig mu;
+  HBig::divmod(HBig::pow2(2 * Mn + 3), qn, &mu, nullptr);
+  if (mu.bitlen() > 32 * f.L) return set_error(MOMA_E_MODULUS, "internal: Barrett constant too wide");
+  mu.to_limbs(f.mu, kMaxLimbs);
+  fe->Q = Q;
+  fe->one_m = one_m;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_fields.find(key);
+  if (it != g_fields.end()) {
+    *out = it->second;
+  } else {
+    g_fields[key] = fe;
+    *out = fe;
+  }
+  return MOMA_OK;
+}
+
+// ------------------------------------------------------------------ transform plans
+
+struct DirTables {
+  uint32_t* tw = nullptr;      // n entries x L words, Montgomery form
+  uint32_t* ladder = nullptr;  // (logn + 1) x L words: w^(2^b) in Montgomery form, then 1
+};
+
+struct NttPlan {
+  std::shared_ptr<FieldEntry> fe;
+  int device = 0;
+  uint64_t n = 0;
+  uint32_t logn = 0;
+  DirTables fwd, inv;
+  NttConsts inv_consts;
+  uint32_t* scratch = nullptr;  // for in-place multi-pass calls
+  std::vector<NttPass> passes;
+  uint32_t threads = 256;
+  std::mutex scratch_mu;
+  ~NttPlan() {
+    (void)hipFree(fwd.tw);
+    (void)hipFree(fwd.ladder);
+    (void)hipFree(inv.tw);
+    (void)hipFree(inv.ladder);
+    (void)hipFree(scratch);
+  }
+};
+
+static std::map<std::vector<uint32_t>, std::shared_ptr<NttPlan>> g_plans;
+
+static std::vector<NttPass> plan_passes(int L, uint32_t logn, uint32_t* threads) {
+  std::vector<NttPass> ps;
+  uint32_t emax = ntt_tile_elems(L);
+  uint32_t loge = 0;
+  while ((1u << (loge + 1)) <= emax) loge++;
+  uint64_t n = 1ull << logn;
+  if (logn <= loge) {
+    ps.push_back({0, logn, 0, 1});
+    uint32_t half = (uint32_t)(n / 2);
+    uint32_t t = half < 64 ? 64 : (half > 256 ? 256 : half);
+    *threads = t;
+    return ps;
+  }
+  uint32_t logc = 4;
+  uint32_t kmax = loge - logc;
+  uint32_t P = (logn + kmax - 1) / kmax;
+  uint32_t base = logn / P, extra = logn % P;
+  uint32_t K = 0;
+  for (uint32_t i = 0; i < P; i++) {
+    uint32_t k = base + (i < extra ? 1 : 0);
+    ps.push_back({K, k, logc, n >> (k + logc)});
+    K += k;
+  }
+  uint32_t half = 1u << (ps[0].k + logc - 1);
+  *threads = half > 256 ? 256 : half;
+  return ps;
+}
+
+static int check_planes(const NttPlan& p) {
+  // every multi-pass split must keep C groups of consecutive addresses
+  for (size_t i = 0; i < p.passes.size(); i++) {
+    const NttPass& s = p.passes[i];
+    if (s.K == 0 && (p.n >> s.k) < (1ull << s.logc)) return -1;
+    if (s.K > 0 && (1ull << s.K) < (1ull << s.logc)) return -1;
+  }
+  return 0;
+}
+
+static int upload(uint32_t** dptr, const std::vector<uint32_t>& host) {
+  int e = (int)hipMalloc((void**)dptr, host.size() * sizeof(uint32_t));
+  if (e) return e;
+  return (int)hipMemcpy(*dptr, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+}
+
+static int build_tables(NttPlan& p, const HBig& w, DirTables* t) {
+  const FieldRaw& f = p.fe->f;
+  const HBig& Q = p.fe->Q;
+  int L = f.L;
+  std::vector<uint32_t> lad((size_t)(p.logn + 1) * L);
+  HBig cur = w;
+  for (uint32_t b = 0; b < p.logn; b++) {
+    HBig m = HBig::mulmod(cur, p.fe->one_m, Q);
+    m.to_limbs(&lad[(size_t)b * L], L);
+    cur = HBig::mulmod(cur, cur, Q);
+  }
+  p.fe->one_m.to_limbs(&lad[(size_t)p.logn * L], L);
+  int e = upload(&t->ladder, lad);
+  if (e) return hip_fail(e, "ladder upload");
+  e = (int)hipMalloc((void**)&t->tw, (size_t)p.n * L * sizeof(uint32_t));
+  if (e) return set_error(MOMA_E_NOMEM, "twiddle table allocation failed");
+  e = launch_twiddle_gen(f, t->tw, p.n, p.logn, t->ladder, 0);
+  if (e) return hip_fail(e, "twiddle generation launch");
+  return MOMA_OK;
+}
+
+static int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
+                    std::shared_ptr<NttPlan>* out) {
+  if (!omega) return set_error(MOMA_E_ARG, "omega is NULL");
+  if (n < 2 || (n & (n - 1)) || n > (1ull << MOMA_MAX_LOG_N))
+    return set_error(MOMA_E_ARG, "n must be a power of two in [2, 2^26], got " + std::to_string(n));
+  std::shared_ptr<FieldEntry> fe;
+  int rc = build_field(q, limbs, &fe);
+  if (rc) return rc;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::vector<uint32_t> key(q, q + limbs);
+  key.insert(key.end(), omega, omega + limbs);
+  key.push_back(limbs);
+  key.push_back((uint32_t)n);
+  key.push_back((uint32_t)(n >> 32));
+  key.push_back((uint32_t)dev);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+      *out = it->second;
+      return MOMA_OK;
+    }
+  }
+  const HBig& Q = fe->Q;
+  HBig W = HBig::from_limbs(omega, (int)limbs);
+  if (HBig::cmp(W, Q) >= 0) return set_error(MOMA_E_ROOT, "omega must be < q");
+  HBig qm1 = HBig::sub(Q, HBig(1));
+  HBig nq, nr;
+  HBig::divmod(qm1, HBig(n), &nq, &nr);
+  if (!nr.is_zero()) return set_error(MOMA_E_ROOT, "n does not divide q - 1");
+  // order exactly n  <=>  w^(n/2) == -1 (n a power of two)
+  if (HBig::cmp(HBig::powmod(W, HBig(n / 2), Q), qm1) != 0)
+    return set_error(MOMA_E_ROOT, "omega^(n/2) != q - 1: omega is not a primitive n-th root of unity");
+  auto p = std::make_shared<NttPlan>();
+  p->fe = fe;
+  p->device = dev;
+  p->n = n;
+  p->logn = 0;
+  while ((1ull << p->logn) < n) p->logn++;
+  p->passes = plan_passes(fe->f.L, p->logn, &p->threads);
+  if (check_planes(*p)) return set_error(MOMA_E_UNSUPPORTED, "no valid pass split for this size");
+  HBig Winv = HBig::powmod(W, HBig(n - 1), Q);
+  HBig ninv = HBig::sub(Q, nq);  // n * (q - (q-1)/n) == 1 mod q
+  HBig nscale = HBig::mulmod(ninv, fe->one_m, Q);
+  memset(&p->inv_consts, 0, sizeof(p->inv_consts));
+  nscale.to_limbs(p->inv_consts.nscale_m, kMaxLimbs);
+  rc = build_tables(*p, W, &p->fwd);
+  if (rc) return rc;
+  rc = build_tables(*p, Winv, &p->inv);
+  if (rc) return rc;
+  int e = (int)hipDeviceSynchronize();
+  if (e) return hip_fail(e, "plan build");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second;
+  } else {
+    g_plans[key] = p;
+    *out = p;
+  }
+  return MOMA_OK;
+}
+
+static int run_ntt(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s) {
+  const FieldRaw& f = p.fe->f;
+  const DirTables& t = inverse ? p.inv : p.fwd;
+  size_t P = p.passes.size();
+  uint32_t* first_out = d_out;
+  if (P > 1 && d_in == d_out) {
+    std::lock_guard<std::mutex> lk(p.scratch_mu);
+    if (!p.scratch) {
+      if (hipMalloc((void**)&p.scratch, (size_t)p.n * f.L * sizeof(uint32_t)))
+        return set_error(MOMA_E_NOMEM, "scratch allocation failed");
+    }
+    first_out = p.scratch;
+  }
+  NttConsts none;
+  memset(&none, 0, sizeof(none));
+  for (size_t i = 0; i < P; i++) {
+    const NttPass& ps = p.passes[i];
+    NttPassArgs a;
+    a.in = (i == 0) ? d_in : (i == 1 ? first_out : d_out);
+    a.out = (i == 0) ? first_out : d_out;
+    a.tw = t.tw;
+    a.n = p.n;
+    a.logn = p.logn;
+    a.K = ps.K;
+    a.k = ps.k;
+    a.logc = ps.logc;
+    a.scale = (inverse && i + 1 == P) ? 1u : 0u;
+    int e = launch_ntt_pass(f, a, inverse ? p.inv_consts : none, p.threads, ps.tiles, s);
+    if (e) return hip_fail(e, "ntt pass launch");
+  }
+  if (f.Ls > f.L && d_out != d_in) {
+    int e = launch_zero_planes(d_out, p.n, f.L, f.Ls, s);
+    if (e) return hip_fail(e, "zero planes launch");
+  }
+  return MOMA_OK;
+}
+
+static int ntt_entry(bool inverse, const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
+                     const uint32_t* d_in, uint32_t* d_out, void* stream) {
+  if (!d_in || !d_out) return set_error(MOMA_E_ARG, "device pointer is NULL");
+  std::shared_ptr<NttPlan> p;
+  int rc = get_plan(q, omega, n, limbs, &p);
+  if (rc) return rc;
+  return run_ntt(*p, inverse, d_in, d_out, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ BLAS
+
+static int blas_entry(int op, const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* alpha,
+                      const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, void* stream) {
+  std::shared_ptr<FieldEntry> fe;
+  int rc = build_field(q, limbs, &fe);
+  if (rc) return rc;
+  if (n > (1ull << 31)) return set_error(MOMA_E_ARG, "n must be <= 2^31");
+  if (n == 0) return MOMA_OK;
+  if (!d_a || !d_b || !d_out) return set_error(MOMA_E_ARG, "device pointer is NULL");
+  BlasArgs a;
+  memset(&a, 0, sizeof(a));
+  a.a = d_a;
+  a.b = d_b;
+  a.out = d_out;
+  a.n = n;
+  if (op == OP_AXPY) {
+    if (!alpha) return set_error(MOMA_E_ARG, "alpha is NULL");
+    std::vector<uint32_t> key(alpha, alpha + limbs);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (fe->alpha_key != key) {
+      HBig A = HBig::from_limbs(alpha, (int)limbs);
+      if (HBig::cmp(A, fe->Q) >= 0) return set_error(MOMA_E_ARG, "alpha must be < q");
+      HBig am = HBig::mulmod(A, fe->one_m, fe->Q);
+      fe->alpha_m.assign(kMaxLimbs, 0);
+      am.to_limbs(fe->alpha_m.data(), kMaxLimbs);
+      fe->alpha_key = key;
+    }
+    memcpy(a.alpha_m, fe->alpha_m.data(), sizeof(a.alpha_m));
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int e = launch_blas(op, fe->f, a, s);
+  if (e) return hip_fail(e, "blas launch");
+  if (fe->f.Ls > fe->f.L) {
+    const uint32_t* ins[2] = {d_a, d_b};
+    bool aliased = ins[0] == d_out || ins[1] == d_out;
+    if (!aliased) {
+      e = launch_zero_planes(d_out, n, fe->f.L, fe->f.Ls, s);
+      if (e) return hip_fail(e, "zero planes launch");
+    }
+  }
+  return MOMA_OK;
+}
+
+}  // namespace moma
+
+using namespace moma;
+
+extern "C" {
+
+const char* moma_strerror(int code) {
+  switch (code) {
+    case MOMA_OK: return "MOMA_OK";
+    case MOMA_E_ARG: return "MOMA_E_ARG: invalid argument";
+    case MOMA_E_MODULUS: return "MOMA_E_MODULUS: invalid modulus";
+    case MOMA_E_ROOT: return "MOMA_E_ROOT: omega is not a primitive n-th root of unity";
+    case MOMA_E_NOMEM: return "MOMA_E_NOMEM: device allocation failed";
+    case MOMA_E_HIP: return "MOMA_E_HIP: HIP runtime error";
+    case MOMA_E_UNSUPPORTED: return "MOMA_E_UNSUPPORTED: unsupported request";
+  }
+  return "unknown error";
+}
+
+const char* moma_last_error_detail(void) { return g_detail.c_str(); }
+
+const char* moma_version(void) { return "moma-mi355x 0.1 (gfx950)"; }
+
+int moma_vadd(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a, const uint32_t* d_b,
+              uint32_t* d_out, void* stream) {
+  return blas_entry(OP_VADD, q, limbs, n, nullptr, d_a, d_b, d_out, stream);
+}
+
+int moma_vsub(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a, const uint32_t* d_b,
+              uint32_t* d_out, void* stream) {
+  return blas_entry(OP_VSUB, q, limbs, n, nullptr, d_a, d_b, d_out, stream);
+}
+
+int moma_vmul(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a, const uint32_t* d_b,
+              uint32_t* d_out, void* stream) {
+  return blas_entry(OP_VMUL, q, limbs, n, nullptr, d_a, d_b, d_out, stream);
+}
+
+int moma_axpy(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* alpha, const uint32_t* d_x,
+              const uint32_t* d_y, uint32_t* d_out, void* stream) {
+  return blas_entry(OP_AXPY, q, limbs, n, alpha, d_x, d_y, d_out, stream);
+}
+
+int moma_ntt_fwd(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const uint32_t* d_in,
+                 uint32_t* d_out, void* stream) {
+  return ntt_entry(false, q, omega, n, limbs, d_in, d_out, stream);
+}
+
+int moma_ntt_inv(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const uint32_t* d_in,
+                 uint32_t* d_out, void* stream) {
+  return ntt_entry(true, q, omega, n, limbs, d_in, d_out, stream);
+}
+
+int moma_ntt_prepare(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs) {
+  std::shared_ptr<NttPlan> p;
+  return get_plan(q, omega, n, limbs, &p);
+}
+
+void moma_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans.clear();
+  g_fields.clear();
+}
+
+}  // extern "C"

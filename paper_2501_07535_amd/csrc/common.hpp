@@ -1,0 +1,73 @@
+// common.hpp - declarations shared by the host runtime and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace moma {
+
+constexpr int kMaxLimbs = 32;
+
+// Constants of one modulus, sized for the largest limb count; the launchers copy
+// the first L words of each array into a compile-time sized kernel argument.
+struct FieldRaw {
+  int L;                   // compute limbs: ceil((bitlen(q) + 4) / 32)
+  int Ls;                  // storage limbs (planes) given by the caller
+  uint32_t q[kMaxLimbs];
+  uint32_t qinv;           // -q^{-1} mod 2^32 (Montgomery)
+  uint32_t one_m[kMaxLimbs];  // 2^(32L) mod q (1 in Montgomery form)
+  uint32_t qn[kMaxLimbs];  // q * 2^d, bitlen 32L - 4 (Barrett)
+  uint32_t mu[kMaxLimbs];  // floor(2^(2(32L-4)+3) / qn)
+  uint32_t d;              // Barrett pre-scale shift
+};
+
+enum BlasOp { OP_VADD = 0, OP_VSUB = 1, OP_VMUL = 2, OP_AXPY = 3 };
+
+struct BlasArgs {
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t* out;
+  uint64_t n;
+  uint32_t alpha_m[kMaxLimbs];  // axpy: alpha * 2^(32L) mod q (Montgomery form)
+};
+
+// One pass of the transform: k radix-2 stages [K, K+k) over tiles of C groups.
+struct NttPass {
+  uint32_t K, k, logc;
+  uint64_t tiles;
+};
+
+struct NttPassArgs {
+  const uint32_t* in;
+  uint32_t* out;
+  const uint32_t* tw;  // twiddle table, element-major, L words per entry
+  uint64_t n;
+  uint32_t logn, K, k, logc;
+  uint32_t scale;      // multiply by n^-1 on store (last pass of the inverse)
+};
+
+struct NttConsts {
+  uint32_t nscale_m[kMaxLimbs];  // n^{-1} * 2^(32L) mod q
+};
+
+// set the thread's error detail and return code
+int set_error(int code, const std::string& detail);
+
+// launchers (return hipError_t as int)
+int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s);
+int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, hipStream_t s);
+int launch_ntt_pass(const FieldRaw& f, const NttPassArgs& a, const NttConsts& c, uint32_t threads, uint64_t tiles,
+                    hipStream_t s);
+int launch_twiddle_gen(const FieldRaw& f, uint32_t* tw, uint64_t n, uint32_t logn, const uint32_t* d_ladder,
+                       hipStream_t s);
+// largest power-of-two element count of one LDS tile for L limbs
+uint32_t ntt_tile_elems(int L);
+
+}  // namespace moma
+
+// expand CASE(L) for every supported compute limb count
+#define MOMA_FOR_EACH_L(CASE)                                                                                     \
+  CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13)    \
+  CASE(14) CASE(15) CASE(16) CASE(17) CASE(18) CASE(19) CASE(20) CASE(21) CASE(22) CASE(23) CASE(24) CASE(25)    \
+  CASE(26) CASE(27) CASE(28) CASE(29) CASE(30) CASE(31) CASE(32)

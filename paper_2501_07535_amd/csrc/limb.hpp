@@ -1,0 +1,273 @@
+// limb.hpp - device-side multi-word modular arithmetic on 32-bit limbs (gfx950).
+//
+// A residue is L little-endian 32-bit limbs held in VGPRs (one lane = one
+// element).  The modulus and its constants are uniform per launch and live in
+// SGPRs (kernel arguments), so every word product has one SGPR operand.
+//
+// The paper decomposes a 2w-bit operation into w-bit operations recursively
+// (Section 3, Table 1).  On gfx950 the machine word is the 32-bit VGPR lane,
+// and the recursion is flattened into straight L-limb loops, unrolled at
+// compile time (L is a template parameter), so no intermediate word size is
+// materialised:
+//   * add / subtract with carry and borrow chains (Section 2.2, rules (adc),
+//     (addqdd), (subddd)) map to v_add_co_u32 / v_addc_co_u32 and
+//     v_sub_co_u32 / v_subb_co_u32, with the carry bit delta held as a
+//     64-bit lane mask in an SGPR pair;
+//   * the conditional selects of Eqs. (saddmod) / (ssubmod) and rule
+//     (moddq_add) map to v_cndmask_b32 on that mask;
+//   * each 32x32->64 word product plus accumulation (rule (mulqdd)) is one
+//     v_mad_u64_u32, whose carry-out feeds a third accumulator word through
+//     one v_addc_co_u32 (product scanning, one column at a time).
+// The instructions are written as small inline-asm statements because the
+// compiler does not use the carry-out of v_mad_u64_u32 on its own; carries
+// between statements travel in named SGPR-pair variables, never in VCC.
+// gfx950 allows one constant-bus (SGPR) read per VALU instruction and the
+// carry-in already uses it, so chained limbs take the modulus from a VGPR copy.
+//
+// Comparisons are canonical (>= q subtracts), not the strict comparisons
+// printed in Eq. (saddmod) and Listing 1, so every output lies in [0, q).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace moma {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+// ----------------------------------------------------------------- word ops
+
+// acc(64) += x * y; hi += carry-out.  x in a VGPR, y in a VGPR.
+__device__ __forceinline__ void mac_vv(u64& acc, u32& hi, u32 x, u32 y) {
+  u64 cy;
+  asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+      "v_addc_co_u32 %2, %1, %2, 0, %1"
+      : "+v"(acc), "=&s"(cy), "+v"(hi)
+      : "v"(x), "v"(y));
+}
+
+// acc(64) += x * y; hi += carry-out.  x in a VGPR, y uniform (SGPR).
+__device__ __forceinline__ void mac_vs(u64& acc, u32& hi, u32 x, u32 y) {
+  u64 cy;
+  asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+      "v_addc_co_u32 %2, %1, %2, 0, %1"
+      : "+v"(acc), "=&s"(cy), "+v"(hi)
+      : "v"(x), "s"(y));
+}
+
+// acc(64) += x * y with no carry-out (caller guarantees no overflow).
+__device__ __forceinline__ void mad_vv(u64& acc, u32 x, u32 y) {
+  u64 cy;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc), "=s"(cy) : "v"(x), "v"(y));
+}
+
+// move the 96-bit column accumulator one word down: {acc, hi} >>= 32
+__device__ __forceinline__ void shift_col(u64& acc, u32& hi) {
+  acc = (acc >> 32) | ((u64)hi << 32);
+  hi = 0;
+}
+
+// r = a + b over L limbs (a, b VGPR); returns the carry-out lane mask
+template <int L>
+__device__ __forceinline__ u64 add_vv(u32* r, const u32* a, const u32* b) {
+  u64 cy;
+  asm("v_add_co_u32 %0, %1, %2, %3" : "=v"(r[0]), "=s"(cy) : "v"(a[0]), "v"(b[0]));
+#pragma unroll
+  for (int i = 1; i < L; i++) asm("v_addc_co_u32 %0, %1, %2, %3, %1" : "=v"(r[i]), "+s"(cy) : "v"(a[i]), "v"(b[i]));
+  return cy;
+}
+
+// r = a + q over L limbs (q uniform); returns the carry-out lane mask
+template <int L>
+__device__ __forceinline__ u64 add_vs(u32* r, const u32* a, const u32* q) {
+  u64 cy;
+  asm("v_add_co_u32 %0, %1, %2, %3" : "=v"(r[0]), "=s"(cy) : "v"(a[0]), "s"(q[0]));
+#pragma unroll
+  for (int i = 1; i < L; i++) asm("v_addc_co_u32 %0, %1, %2, %3, %1" : "=v"(r[i]), "+s"(cy) : "v"(a[i]), "v"(q[i]));
+  return cy;
+}
+
+// r = a - b over L limbs (a, b VGPR); returns the borrow-out lane mask
+template <int L>
+__device__ __forceinline__ u64 sub_vv(u32* r, const u32* a, const u32* b) {
+  u64 br;
+  asm("v_sub_co_u32 %0, %1, %2, %3" : "=v"(r[0]), "=s"(br) : "v"(a[0]), "v"(b[0]));
+#pragma unroll
+  for (int i = 1; i < L; i++) asm("v_subb_co_u32 %0, %1, %2, %3, %1" : "=v"(r[i]), "+s"(br) : "v"(a[i]), "v"(b[i]));
+  return br;
+}
+
+// r = a - q over L limbs (q uniform); returns the borrow-out lane mask
+template <int L>
+__device__ __forceinline__ u64 sub_vs(u32* r, const u32* a, const u32* q) {
+  u64 br;
+  asm("v_sub_co_u32 %0, %1, %2, %3" : "=v"(r[0]), "=s"(br) : "v"(a[0]), "s"(q[0]));
+#pragma unroll
+  for (int i = 1; i < L; i++) asm("v_subb_co_u32 %0, %1, %2, %3, %1" : "=v"(r[i]), "+s"(br) : "v"(a[i]), "v"(q[i]));
+  return br;
+}
+
+// r[i] = mask ? x[i] : y[i] per lane
+template <int L>
+__device__ __forceinline__ void select(u32* r, u64 mask, const u32* x, const u32* y) {
+#pragma unroll
+  for (int i = 0; i < L; i++) asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r[i]) : "v"(y[i]), "v"(x[i]), "s"(mask));
+}
+
+// ----------------------------------------------------------------- modular ops
+
+// r = (a + b) mod q for a, b in [0, q), q < 2^(32L-1): sum, trial subtraction, select.
+template <int L>
+__device__ __forceinline__ void mod_add(u32* r, const u32* a, const u32* b, const u32* q) {
+  u32 s[L], d[L];
+  add_vv<L>(s, a, b);            // no carry-out: a + b < 2q < 2^(32L)
+  u64 br = sub_vs<L>(d, s, q);   // borrow set  <=>  s < q
+  select<L>(r, br, s, d);
+}
+
+// r = (a - b) mod q for a, b in [0, q): difference, add q back where it borrowed.
+template <int L>
+__device__ __forceinline__ void mod_sub(u32* r, const u32* a, const u32* b, const u32* q) {
+  u32 d[L], e[L];
+  u64 br = sub_vv<L>(d, a, b);
+  add_vs<L>(e, d, q);
+  select<L>(r, br, e, d);
+}
+
+// r = x mod q for x in [0, 2q): one trial subtraction.
+template <int L>
+__device__ __forceinline__ void reduce_once(u32* r, const u32* x, const u32* q) {
+  u32 d[L];
+  u64 br = sub_vs<L>(d, x, q);
+  select<L>(r, br, x, d);
+}
+
+// Montgomery product r = a * b * 2^(-32L) mod q (Montgomery, Math. Comp. 1985),
+// product-scanning form: column i accumulates every a_j*b_{i-j} and m_j*q_{i-j},
+// then m_i = (column low word) * (-q^-1 mod 2^32) zeroes the low word.
+// a, b in [0, q); q < 2^(32L-1); qinv = -q^{-1} mod 2^32.  Result in [0, q).
+// 2L^2 + L word products (as counted for Montgomery multiplication).
+template <int L>
+__device__ __forceinline__ void mont_mul(u32* r, const u32* a, const u32* b, const u32* q, u32 qinv) {
+  u32 m[L];
+  u64 acc = 0;
+  u32 hi = 0;
+#pragma unroll
+  for (int i = 0; i < L; i++) {
+#pragma unroll
+    for (int j = 0; j < i; j++) {
+      mac_vv(acc, hi, a[j], b[i - j]);
+      mac_vs(acc, hi, m[j], q[i - j]);
+    }
+    mac_vv(acc, hi, a[i], b[0]);
+    m[i] = (u32)acc * qinv;
+    mac_vs(acc, hi, m[i], q[0]);
+    shift_col(acc, hi);
+  }
+  u32 t[L];
+#pragma unroll
+  for (int i = L; i < 2 * L; i++) {
+#pragma unroll
+    for (int j = i - L + 1; j < L; j++) {
+      mac_vv(acc, hi, a[j], b[i - j]);
+      mac_vs(acc, hi, m[j], q[i - j]);
+    }
+    t[i - L] = (u32)acc;
+    shift_col(acc, hi);
+  }
+  // (ab + mq) / 2^(32L) < 2q < 2^(32L): the final carry word is zero
+  reduce_once<L>(r, t, q);
+}
+
+// Barrett constants for r = a*b mod q, following Listings 1 and 4 generalised to
+// L limbs.  The modulus is pre-scaled to qn = q * 2^d with bitlen(qn) = M = 32L-4,
+// so the paper's shifts by M-2 and M+5 fall at fixed limb/bit positions:
+// mu = floor(2^(2M+3) / qn) < 2^(M+4) = 2^(32L).
+template <int L>
+struct BarrettC {
+  u32 qn[L];
+  u32 mu[L];
+  u32 d;
+};
+
+// r = a*b mod q by Barrett reduction (Eq. (barrett), Listing 4 generalised):
+//   a' = a*2^d, t = a'*b < qn^2, r1 = t >> (M-2), r2 = (r1*mu) >> (M+5),
+//   t - r2*qn in [0, 2qn) (one correction), result = (that mod qn) >> d.
+// The subtraction uses only the low L limbs, as in _dmulmod: the difference
+// fits in L limbs.  Products: L^2 (a*b) + L^2 (r1*mu) + L(L+1)/2 (r2*qn).
+template <int L>
+__device__ __forceinline__ void barrett_mul(u32* r, const u32* a, const u32* b, const BarrettC<L>& c) {
+  // a' = a << d (a < q so a' < qn < 2^(32L-4): no overflow past L limbs)
+  u32 as[L];
+  if (c.d == 0) {
+#pragma unroll
+    for (int i = 0; i < L; i++) as[i] = a[i];
+  } else {
+    as[0] = a[0] << c.d;
+#pragma unroll
+    for (int i = 1; i < L; i++) as[i] = __builtin_amdgcn_alignbit(a[i], a[i - 1], 32 - c.d);
+  }
+  // t = a' * b, 2L limbs, product scanning
+  u32 t[2 * L];
+  {
+    u64 acc = 0;
+    u32 hi = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * L - 1; k++) {
+#pragma unroll
+      for (int i = (k < L ? 0 : k - L + 1); i <= (k < L ? k : L - 1); i++) mac_vv(acc, hi, as[i], b[k - i]);
+      t[k] = (u32)acc;
+      shift_col(acc, hi);
+    }
+    t[2 * L - 1] = (u32)acc;
+  }
+  // r1 = t >> (M - 2) = t >> (32(L-1) + 26): limbs L-1 .. 2L-1, bit offset 26
+  u32 r1[L];
+#pragma unroll
+  for (int i = 0; i < L; i++) r1[i] = __builtin_amdgcn_alignbit(t[L + i], t[L - 1 + i], 26);
+  // r2 = (r1 * mu) >> (M + 5) = >> (32L + 1): need product limbs L .. 2L-1 exactly
+  u32 p[2 * L];
+  {
+    u64 acc = 0;
+    u32 hi = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * L - 1; k++) {
+#pragma unroll
+      for (int i = (k < L ? 0 : k - L + 1); i <= (k < L ? k : L - 1); i++) mac_vs(acc, hi, r1[i], c.mu[k - i]);
+      p[k] = (u32)acc;
+      shift_col(acc, hi);
+    }
+    p[2 * L - 1] = (u32)acc;
+  }
+  u32 r2[L];
+#pragma unroll
+  for (int i = 0; i < L - 1; i++) r2[i] = __builtin_amdgcn_alignbit(p[L + i + 1], p[L + i], 1);
+  r2[L - 1] = p[2 * L - 1] >> 1;
+  // low L limbs of r2 * qn
+  u32 s[L];
+  {
+    u64 acc = 0;
+    u32 hi = 0;
+#pragma unroll
+    for (int k = 0; k < L; k++) {
+#pragma unroll
+      for (int i = 0; i <= k; i++) mac_vs(acc, hi, r2[i], c.qn[k - i]);
+      s[k] = (u32)acc;
+      shift_col(acc, hi);
+    }
+  }
+  u32 dlt[L], red[L];
+  sub_vv<L>(dlt, t, s);               // t - r2*qn mod 2^(32L), true value in [0, 2qn)
+  reduce_once<L>(red, dlt, c.qn);
+  // undo the scaling: exact, the low d bits are zero
+  if (c.d == 0) {
+#pragma unroll
+    for (int i = 0; i < L; i++) r[i] = red[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < L - 1; i++) r[i] = __builtin_amdgcn_alignbit(red[i + 1], red[i], c.d);
+    r[L - 1] = red[L - 1] >> c.d;
+  }
+}
+
+}  // namespace moma

@@ -1,0 +1,129 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/moma.h declares, and rejects invalid arguments on the host before any
+HIP call (every case here fails validation, so no kernel is ever launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "moma.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(moma_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("moma_ntt_fwd", "moma_ntt_inv", "moma_vadd", "moma_vsub", "moma_vmul", "moma_axpy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(moma.EXPORTED) <= set(declared_functions())
+
+
+def test_product_path_does_not_reference_oracle():
+    pkg = os.path.join(ROOT, "paper_2501_07535_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), f
+
+
+def _w(v, L):
+    return (ctypes.c_uint32 * L)(*[(v >> (32 * j)) & 0xFFFFFFFF for j in range(L)])
+
+
+DUMMY = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+
+
+def test_error_codes_and_strings():
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    assert lib.moma_strerror(0) == b"MOMA_OK"
+    for code in (-1, -2, -3, -4, -5, -6):
+        assert lib.moma_strerror(code).startswith(b"MOMA_E_")
+    assert b"gfx950" in lib.moma_version()
+
+
+@pytest.mark.parametrize("case", ["limbs_low", "limbs_high", "q_even", "q_too_wide", "q_null", "q_small"])
+def test_blas_rejects_bad_modulus(case):
+    import moma_inputs as mi
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    f = mi.find_prime(256, 0)
+    L, q = 8, f.q
+    if case == "limbs_low":
+        rc = lib.moma_vadd(_w(q, 8), 1, 10, DUMMY, DUMMY, DUMMY, None)
+        assert rc == moma.MOMA_E_ARG
+    elif case == "limbs_high":
+        rc = lib.moma_vadd(_w(q, 33), 33, 10, DUMMY, DUMMY, DUMMY, None)
+        assert rc == moma.MOMA_E_ARG
+    elif case == "q_even":
+        rc = lib.moma_vmul(_w(q + 1, L), L, 10, DUMMY, DUMMY, DUMMY, None)
+        assert rc == moma.MOMA_E_MODULUS
+    elif case == "q_too_wide":
+        wide = (1 << 253) + 1                      # 254 bits > 32*8-4
+        rc = lib.moma_vsub(_w(wide, L), L, 10, DUMMY, DUMMY, DUMMY, None)
+        assert rc == moma.MOMA_E_MODULUS
+    elif case == "q_null":
+        rc = lib.moma_vadd(None, L, 10, DUMMY, DUMMY, DUMMY, None)
+        assert rc == moma.MOMA_E_ARG
+    elif case == "q_small":
+        rc = lib.moma_vadd(_w(1, L), L, 10, DUMMY, DUMMY, DUMMY, None)
+        assert rc == moma.MOMA_E_MODULUS
+    assert lib.moma_last_error_detail()
+
+
+def test_blas_rejects_null_vectors_and_bad_alpha():
+    import moma_inputs as mi
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    f = mi.find_prime(256, 0)
+    assert lib.moma_vadd(_w(f.q, 8), 8, 10, None, DUMMY, DUMMY, None) == moma.MOMA_E_ARG
+    assert lib.moma_axpy(_w(f.q, 8), 8, 10, None, DUMMY, DUMMY, DUMMY, None) == moma.MOMA_E_ARG
+    assert lib.moma_axpy(_w(f.q, 8), 8, 10, _w(f.q, 8), DUMMY, DUMMY, DUMMY, None) == moma.MOMA_E_ARG
+    assert lib.moma_vadd(_w(f.q, 8), 8, (1 << 31) + 1, DUMMY, DUMMY, DUMMY, None) == moma.MOMA_E_ARG
+    # n == 0 is a no-op that touches nothing
+    assert lib.moma_vmul(_w(f.q, 8), 8, 0, None, None, None, None) == 0
+
+
+@pytest.mark.parametrize("case", ["n_not_pow2", "n_too_big", "n_one", "omega_order", "omega_ge_q", "omega_null",
+                                  "n_not_dividing"])
+def test_ntt_rejects_bad_arguments(case):
+    import moma_inputs as mi
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    f = mi.find_prime(256, 0)
+    q, L, n = f.q, 8, 1 << 10
+    w = f.root(n)
+    want = moma.MOMA_E_ARG
+    if case == "n_not_pow2":
+        args = (_w(q, L), _w(w, L), 1000)
+    elif case == "n_too_big":
+        args = (_w(q, L), _w(w, L), 1 << 27)
+    elif case == "n_one":
+        args = (_w(q, L), _w(w, L), 1)
+    elif case == "omega_order":
+        args, want = (_w(q, L), _w(f.root(n // 2), L), n), moma.MOMA_E_ROOT   # order n/2, not n
+    elif case == "omega_ge_q":
+        args, want = (_w(q, L), _w(q, L), n), moma.MOMA_E_ROOT
+    elif case == "omega_null":
+        args = (_w(q, L), None, n)
+    else:   # n = 2^33 does not divide q - 1 (2-adicity 33) -> too big anyway; use a prime with small 2-adicity
+        q2 = 1000000007                                 # q2 - 1 = 2 * 500000003
+        args, want = (_w(q2, 2), _w(q2 - 1, 2), 4), moma.MOMA_E_ROOT
+        assert lib.moma_ntt_fwd(*args, 2, DUMMY, DUMMY, None) == want
+        return
+    assert lib.moma_ntt_fwd(*args, L, DUMMY, DUMMY, None) == want
+    assert lib.moma_ntt_inv(*args, L, DUMMY, DUMMY, None) == want
+    assert lib.moma_ntt_prepare(*args, L) == want
