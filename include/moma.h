@@ -111,6 +111,42 @@ int moma_ntt_inv(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t 
  */
 int moma_ntt_prepare(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs);
 
+/*
+ * Describe the schedule of the plan for (q, omega, n, limbs): the number of
+ * kernel launches (passes) per transform, the stages each pass runs, and the
+ * compute limb count.  pass_stages must hold max_passes entries; entries past
+ * *npasses are left untouched.  Builds the plan if needed.
+ */
+int moma_ntt_describe(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, uint32_t* npasses,
+                      uint32_t* pass_stages, uint32_t max_passes, uint32_t* compute_limbs);
+
+/*
+ * Launch shape of a transform plan (the knobs the autotuner searches):
+ *   tile_log  - log2 of the elements one workgroup keeps in LDS (LDS bytes =
+ *               4 * compute_limbs * 2^tile_log, at most 160 KiB);
+ *   col_log   - log2 of the coalesced groups per tile in multi-pass plans;
+ *               passes run tile_log - col_log stages each;
+ *   threads   - threads per workgroup, a multiple of 64 in [64, 1024];
+ *   radix_log - stages each thread runs in registers per LDS round trip
+ *               (radix 2, 4 or 8; radix 8 up to 8 limbs, radix 4 up to 12).
+ * Every schedule computes the same result; only speed differs.
+ */
+typedef struct moma_ntt_schedule {
+  uint32_t tile_log;
+  uint32_t col_log;
+  uint32_t threads;
+  uint32_t radix_log;
+} moma_ntt_schedule_t;
+
+/* Set the schedule of the plan for (q, omega, n, limbs); NULL restores the
+ * default.  MOMA_E_UNSUPPORTED if the shape cannot run this size, MOMA_E_ARG
+ * for malformed values.  Affects calls enqueued afterwards. */
+int moma_ntt_set_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
+                          const moma_ntt_schedule_t* sched);
+/* Read the schedule the plan currently uses. */
+int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
+                          moma_ntt_schedule_t* sched);
+
 /* Free every cached plan and device table.  Safe to call more than once. */
 void moma_shutdown(void);
 

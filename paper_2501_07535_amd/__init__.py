@@ -56,6 +56,24 @@ for _name in ("moma_ntt_fwd", "moma_ntt_inv"):
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.moma_ntt_prepare.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32]
 _lib.moma_ntt_prepare.restype = ctypes.c_int
+_lib.moma_ntt_describe.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _u32p, _u32p, ctypes.c_uint32,
+                                   _u32p]
+_lib.moma_ntt_describe.restype = ctypes.c_int
+
+
+class Schedule(ctypes.Structure):
+    """Launch shape of a transform plan (see moma_ntt_schedule_t)."""
+    _fields_ = [("tile_log", ctypes.c_uint32), ("col_log", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("radix_log", ctypes.c_uint32)]
+
+    def as_tuple(self):
+        return (self.tile_log, self.col_log, self.threads, self.radix_log)
+
+
+_lib.moma_ntt_set_schedule.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Schedule)]
+_lib.moma_ntt_set_schedule.restype = ctypes.c_int
+_lib.moma_ntt_get_schedule.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Schedule)]
+_lib.moma_ntt_get_schedule.restype = ctypes.c_int
 _lib.moma_strerror.argtypes = [ctypes.c_int]
 _lib.moma_strerror.restype = ctypes.c_char_p
 _lib.moma_last_error_detail.restype = ctypes.c_char_p
@@ -65,7 +83,8 @@ _lib.moma_shutdown.restype = None
 MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
-            "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_prepare", "moma_shutdown")
+            "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_prepare", "moma_ntt_describe",
+            "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_shutdown")
 
 
 class MomaError(RuntimeError):
@@ -185,6 +204,30 @@ def ntt_inv(y, q: int, omega: int, out=None, stream=None):
 def ntt_prepare(q: int, omega: int, n: int, limbs: int):
     """Build the plan (twiddle tables) for (q, omega, n, limbs) ahead of timed calls."""
     _check(_lib.moma_ntt_prepare(_words(q, limbs), _words(omega, limbs), n, limbs))
+
+
+def ntt_describe(q: int, omega: int, n: int, limbs: int) -> dict:
+    """Schedule of the plan: passes (kernel launches) per transform and stages per pass."""
+    npasses, climbs = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    stages = (ctypes.c_uint32 * 16)()
+    _check(_lib.moma_ntt_describe(_words(q, limbs), _words(omega, limbs), n, limbs, ctypes.byref(npasses), stages,
+                                  16, ctypes.byref(climbs)))
+    return {"passes": int(npasses.value), "stages": [int(stages[i]) for i in range(npasses.value)],
+            "compute_limbs": int(climbs.value)}
+
+
+def ntt_set_schedule(q: int, omega: int, n: int, limbs: int, sched=None):
+    """Set the plan's launch shape: a (tile_log, col_log, threads, radix_log) tuple, or None for the default."""
+    ptr = None
+    if sched is not None:
+        ptr = ctypes.byref(Schedule(*[int(v) for v in sched]))
+    _check(_lib.moma_ntt_set_schedule(_words(q, limbs), _words(omega, limbs), n, limbs, ptr))
+
+
+def ntt_get_schedule(q: int, omega: int, n: int, limbs: int) -> tuple:
+    s = Schedule()
+    _check(_lib.moma_ntt_get_schedule(_words(q, limbs), _words(omega, limbs), n, limbs, ctypes.byref(s)))
+    return s.as_tuple()
 
 
 def shutdown():

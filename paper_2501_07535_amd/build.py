@@ -1,5 +1,8 @@
 """Build libmoma.so (HIP for gfx950) in place, next to this file.
 
+Run as a script (python paper_2501_07535_amd/build.py) or through
+__graft_entry__.build(); importing the package itself needs a built library.
+
 Each source is compiled by hipcc in its own process (they run in parallel),
 then linked into one shared library exporting the C ABI of include/moma.h.
 """

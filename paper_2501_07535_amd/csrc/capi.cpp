@@ -3,6 +3,7 @@
 // and the extern "C" entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -106,9 +107,9 @@ struct NttPlan {
   DirTables fwd, inv;
   NttConsts inv_consts;
   uint32_t* scratch = nullptr;  // for in-place multi-pass calls
+  NttSchedule sched;
   std::vector<NttPass> passes;
-  uint32_t threads = 256;
-  std::mutex scratch_mu;
+  std::mutex mu;  // guards scratch allocation and schedule changes
   ~NttPlan() {
     (void)hipFree(fwd.tw);
     (void)hipFree(fwd.ladder);
@@ -120,38 +121,79 @@ struct NttPlan {
 
 static std::map<std::vector<uint32_t>, std::shared_ptr<NttPlan>> g_plans;
 
-static std::vector<NttPass> plan_passes(int L, uint32_t logn, uint32_t* threads) {
+static uint32_t max_radix_log(int L) {
+  return L <= kMaxLimbsRadix8 ? 3u : (L <= kMaxLimbsRadix4 ? 2u : 1u);
+}
+
+// Split log2 n stages into passes for a schedule; returns MOMA_OK or an error
+// code when the schedule cannot run this size.
+static int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out) {
+  if (s.threads < 64 || s.threads > 1024 || s.threads % 64)
+    return set_error(MOMA_E_ARG, "threads must be a multiple of 64 in [64, 1024]");
+  if (s.radix_log < 1 || s.radix_log > max_radix_log(L))
+    return set_error(MOMA_E_UNSUPPORTED, "radix_log out of range for this limb count");
+  if (s.threads > ntt_max_threads(L, s.radix_log))
+    return set_error(MOMA_E_UNSUPPORTED, "too many threads for this limb count and radix");
+  if (s.tile_log < 1 || s.tile_log > 20) return set_error(MOMA_E_ARG, "tile_log out of range");
+  if (((uint64_t)L << s.tile_log) * 4 > 160 * 1024)
+    return set_error(MOMA_E_UNSUPPORTED, "tile exceeds the 160 KiB LDS of a compute unit");
   std::vector<NttPass> ps;
-  uint32_t emax = ntt_tile_elems(L);
-  uint32_t loge = 0;
-  while ((1u << (loge + 1)) <= emax) loge++;
   uint64_t n = 1ull << logn;
-  if (logn <= loge) {
+  if (logn <= s.tile_log) {
     ps.push_back({0, logn, 0, 1});
-    uint32_t half = (uint32_t)(n / 2);
-    uint32_t t = half < 64 ? 64 : (half > 256 ? 256 : half);
-    *threads = t;
-    return ps;
+  } else {
+    if (s.col_log < 1 || s.col_log + 1 > s.tile_log) return set_error(MOMA_E_ARG, "col_log out of range");
+    uint32_t kmax = s.tile_log - s.col_log;
+    uint32_t P = (logn + kmax - 1) / kmax;
+    uint32_t base = logn / P, extra = logn % P;
+    uint32_t K = 0;
+    for (uint32_t i = 0; i < P; i++) {
+      uint32_t k = base + (i < extra ? 1 : 0);
+      // the C groups of a tile need C offsets (first pass) or C blocks (later passes)
+      if (K == 0 && logn - k < s.col_log) return set_error(MOMA_E_UNSUPPORTED, "first pass too wide");
+      if (K > 0 && K < s.col_log) return set_error(MOMA_E_UNSUPPORTED, "pass needs more blocks than columns");
+      ps.push_back({K, k, s.col_log, n >> (k + s.col_log)});
+      K += k;
+    }
   }
-  uint32_t logc = 4;
-  uint32_t kmax = loge - logc;
-  uint32_t P = (logn + kmax - 1) / kmax;
-  uint32_t base = logn / P, extra = logn % P;
-  uint32_t K = 0;
-  for (uint32_t i = 0; i < P; i++) {
-    uint32_t k = base + (i < extra ? 1 : 0);
-    ps.push_back({K, k, logc, n >> (k + logc)});
-    K += k;
+  *out = ps;
+  return MOMA_OK;
+}
+
+// Default launch shape, first feasible of: one pass when the whole transform
+// fits a 64 KiB tile; otherwise 32 KiB tiles (several workgroups per CU) with
+// 16, 8 or 4 coalesced columns.  Radix-4 register units where the VGPR budget
+// allows, and enough threads to give each one or two units per round.
+static NttSchedule default_schedule(int L, uint32_t logn) {
+  auto lg = [](uint32_t words) {
+    uint32_t t = 0;
+    while ((2u << t) <= words) t++;
+    return t;
+  };
+  uint32_t t64 = lg(16384u / (uint32_t)L), t32 = lg(8192u / (uint32_t)L);
+  uint32_t radix = std::min(2u, max_radix_log(L));
+  std::vector<NttSchedule> cands;
+  if (logn <= t64) cands.push_back({logn, 0, 0, radix});
+  for (uint32_t cl : {4u, 3u, 2u}) cands.push_back({t32, cl, 0, radix});
+  for (uint32_t cl : {4u, 3u, 2u, 1u}) cands.push_back({t64, cl, 0, radix});
+  std::string keep = g_detail;
+  for (NttSchedule s : cands) {
+    uint32_t e = std::min(logn, s.tile_log);
+    uint32_t units = 1u << (e > s.radix_log ? e - s.radix_log : 0);
+    uint32_t t = std::min(units > 256 ? 256u : units, ntt_max_threads(L, s.radix_log));
+    s.threads = t < 64 ? 64 : (t + 63) / 64 * 64;
+    std::vector<NttPass> ps;
+    if (plan_passes(L, logn, s, &ps) == MOMA_OK) {
+      g_detail = keep;
+      return s;
+    }
   }
-  uint32_t half = 1u << (ps[0].k + logc - 1);
-  *threads = half > 256 ? 256 : half;
-  return ps;
+  g_detail = keep;
+  return cands.back();
 }
 
 static int check_planes(const NttPlan& p) {
-  // every multi-pass split must keep C groups of consecutive addresses
-  for (size_t i = 0; i < p.passes.size(); i++) {
-    const NttPass& s = p.passes[i];
+  for (const NttPass& s : p.passes) {
     if (s.K == 0 && (p.n >> s.k) < (1ull << s.logc)) return -1;
     if (s.K > 0 && (1ull << s.K) < (1ull << s.logc)) return -1;
   }
@@ -225,7 +267,9 @@ static int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32
   p->n = n;
   p->logn = 0;
   while ((1ull << p->logn) < n) p->logn++;
-  p->passes = plan_passes(fe->f.L, p->logn, &p->threads);
+  p->sched = default_schedule(fe->f.L, p->logn);
+  rc = plan_passes(fe->f.L, p->logn, p->sched, &p->passes);
+  if (rc) return rc;
   if (check_planes(*p)) return set_error(MOMA_E_UNSUPPORTED, "no valid pass split for this size");
   HBig Winv = HBig::powmod(W, HBig(n - 1), Q);
   HBig ninv = HBig::sub(Q, nq);  // n * (q - (q-1)/n) == 1 mod q
@@ -252,20 +296,26 @@ static int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32
 static int run_ntt(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s) {
   const FieldRaw& f = p.fe->f;
   const DirTables& t = inverse ? p.inv : p.fwd;
-  size_t P = p.passes.size();
+  std::vector<NttPass> passes;
+  NttSchedule sched;
   uint32_t* first_out = d_out;
-  if (P > 1 && d_in == d_out) {
-    std::lock_guard<std::mutex> lk(p.scratch_mu);
-    if (!p.scratch) {
-      if (hipMalloc((void**)&p.scratch, (size_t)p.n * f.L * sizeof(uint32_t)))
-        return set_error(MOMA_E_NOMEM, "scratch allocation failed");
+  {
+    std::lock_guard<std::mutex> lk(p.mu);
+    passes = p.passes;
+    sched = p.sched;
+    if (passes.size() > 1 && d_in == d_out) {
+      if (!p.scratch) {
+        if (hipMalloc((void**)&p.scratch, (size_t)p.n * f.L * sizeof(uint32_t)))
+          return set_error(MOMA_E_NOMEM, "scratch allocation failed");
+      }
+      first_out = p.scratch;
     }
-    first_out = p.scratch;
   }
+  size_t P = passes.size();
   NttConsts none;
   memset(&none, 0, sizeof(none));
   for (size_t i = 0; i < P; i++) {
-    const NttPass& ps = p.passes[i];
+    const NttPass& ps = passes[i];
     NttPassArgs a;
     a.in = (i == 0) ? d_in : (i == 1 ? first_out : d_out);
     a.out = (i == 0) ? first_out : d_out;
@@ -275,8 +325,9 @@ static int run_ntt(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_o
     a.K = ps.K;
     a.k = ps.k;
     a.logc = ps.logc;
+    a.last = (i + 1 == P) ? 1u : 0u;
     a.scale = (inverse && i + 1 == P) ? 1u : 0u;
-    int e = launch_ntt_pass(f, a, inverse ? p.inv_consts : none, p.threads, ps.tiles, s);
+    int e = launch_ntt_pass(f, a, inverse ? p.inv_consts : none, sched.threads, ps.tiles, sched.radix_log, s);
     if (e) return hip_fail(e, "ntt pass launch");
   }
   if (f.Ls > f.L && d_out != d_in) {
@@ -395,6 +446,49 @@ int moma_ntt_inv(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t 
 int moma_ntt_prepare(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs) {
   std::shared_ptr<NttPlan> p;
   return get_plan(q, omega, n, limbs, &p);
+}
+
+int moma_ntt_describe(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, uint32_t* npasses,
+                      uint32_t* pass_stages, uint32_t max_passes, uint32_t* compute_limbs) {
+  if (!npasses) return set_error(MOMA_E_ARG, "npasses is NULL");
+  std::shared_ptr<NttPlan> p;
+  int rc = get_plan(q, omega, n, limbs, &p);
+  if (rc) return rc;
+  *npasses = (uint32_t)p->passes.size();
+  if (pass_stages)
+    for (uint32_t i = 0; i < max_passes && i < p->passes.size(); i++) pass_stages[i] = p->passes[i].k;
+  if (compute_limbs) *compute_limbs = (uint32_t)p->fe->f.L;
+  return MOMA_OK;
+}
+
+int moma_ntt_set_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
+                          const moma_ntt_schedule_t* sched) {
+  std::shared_ptr<NttPlan> p;
+  int rc = get_plan(q, omega, n, limbs, &p);
+  if (rc) return rc;
+  NttSchedule s = sched ? NttSchedule{sched->tile_log, sched->col_log, sched->threads, sched->radix_log}
+                        : default_schedule(p->fe->f.L, p->logn);
+  std::vector<NttPass> ps;
+  rc = plan_passes(p->fe->f.L, p->logn, s, &ps);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->sched = s;
+  p->passes = ps;
+  return MOMA_OK;
+}
+
+int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
+                          moma_ntt_schedule_t* sched) {
+  if (!sched) return set_error(MOMA_E_ARG, "sched is NULL");
+  std::shared_ptr<NttPlan> p;
+  int rc = get_plan(q, omega, n, limbs, &p);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(p->mu);
+  sched->tile_log = p->sched.tile_log;
+  sched->col_log = p->sched.col_log;
+  sched->threads = p->sched.threads;
+  sched->radix_log = p->sched.radix_log;
+  return MOMA_OK;
 }
 
 void moma_shutdown(void) {

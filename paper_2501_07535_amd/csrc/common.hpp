@@ -8,6 +8,9 @@
 namespace moma {
 
 constexpr int kMaxLimbs = 32;
+// widest limb counts that get radix-4 / radix-8 register units
+constexpr int kMaxLimbsRadix4 = 12;
+constexpr int kMaxLimbsRadix8 = 8;
 
 // Constants of one modulus, sized for the largest limb count; the launchers copy
 // the first L words of each array into a compile-time sized kernel argument.
@@ -44,7 +47,15 @@ struct NttPassArgs {
   const uint32_t* tw;  // twiddle table, element-major, L words per entry
   uint64_t n;
   uint32_t logn, K, k, logc;
+  uint32_t last;       // last pass: store canonical residues in [0, q)
   uint32_t scale;      // multiply by n^-1 on store (last pass of the inverse)
+};
+
+// Launch shape of a transform: LDS tile of 2^tile_log elements, 2^col_log
+// groups per tile in multi-pass plans, threads per workgroup, and stages per
+// register unit (radix 2^radix_log).
+struct NttSchedule {
+  uint32_t tile_log, col_log, threads, radix_log;
 };
 
 struct NttConsts {
@@ -58,11 +69,12 @@ int set_error(int code, const std::string& detail);
 int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s);
 int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, hipStream_t s);
 int launch_ntt_pass(const FieldRaw& f, const NttPassArgs& a, const NttConsts& c, uint32_t threads, uint64_t tiles,
-                    hipStream_t s);
+                    uint32_t radix_log, hipStream_t s);
+// largest workgroup the pass kernel for (L, radix_log) was compiled for
+uint32_t ntt_max_threads(int L, uint32_t radix_log);
 int launch_twiddle_gen(const FieldRaw& f, uint32_t* tw, uint64_t n, uint32_t logn, const uint32_t* d_ladder,
                        hipStream_t s);
-// largest power-of-two element count of one LDS tile for L limbs
-uint32_t ntt_tile_elems(int L);
+
 
 }  // namespace moma
 

@@ -142,13 +142,14 @@ __device__ __forceinline__ void reduce_once(u32* r, const u32* x, const u32* q) 
   select<L>(r, br, x, d);
 }
 
-// Montgomery product r = a * b * 2^(-32L) mod q (Montgomery, Math. Comp. 1985),
-// product-scanning form: column i accumulates every a_j*b_{i-j} and m_j*q_{i-j},
-// then m_i = (column low word) * (-q^-1 mod 2^32) zeroes the low word.
-// a, b in [0, q); q < 2^(32L-1); qinv = -q^{-1} mod 2^32.  Result in [0, q).
+// Montgomery product t = a * b * 2^(-32L) (mod q), left in [0, 2q) (Montgomery,
+// Math. Comp. 1985), product-scanning form: column i accumulates every a_j*b_{i-j}
+// and m_j*q_{i-j}, then m_i = (column low word) * (-q^-1 mod 2^32) zeroes the low
+// word.  Requires a*b < 4q^2 (e.g. a < 4q, b < q) and 4q <= 2^(32L); then
+// t = (ab + mq) / 2^(32L) < 2q.  qinv = -q^{-1} mod 2^32.
 // 2L^2 + L word products (as counted for Montgomery multiplication).
 template <int L>
-__device__ __forceinline__ void mont_mul(u32* r, const u32* a, const u32* b, const u32* q, u32 qinv) {
+__device__ __forceinline__ void mont_mul_lazy(u32* t, const u32* a, const u32* b, const u32* q, u32 qinv) {
   u32 m[L];
   u64 acc = 0;
   u32 hi = 0;
@@ -164,7 +165,6 @@ __device__ __forceinline__ void mont_mul(u32* r, const u32* a, const u32* b, con
     mac_vs(acc, hi, m[i], q[0]);
     shift_col(acc, hi);
   }
-  u32 t[L];
 #pragma unroll
   for (int i = L; i < 2 * L; i++) {
 #pragma unroll
@@ -175,8 +175,31 @@ __device__ __forceinline__ void mont_mul(u32* r, const u32* a, const u32* b, con
     t[i - L] = (u32)acc;
     shift_col(acc, hi);
   }
-  // (ab + mq) / 2^(32L) < 2q < 2^(32L): the final carry word is zero
+  // t < 2q < 2^(32L): the final carry word is zero
+}
+
+// Montgomery product reduced to [0, q): a, b in [0, q).
+template <int L>
+__device__ __forceinline__ void mont_mul(u32* r, const u32* a, const u32* b, const u32* q, u32 qinv) {
+  u32 t[L];
+  mont_mul_lazy<L>(t, a, b, q, qinv);
   reduce_once<L>(r, t, q);
+}
+
+// Cooley-Tukey butterfly with lazy reduction (Harvey, "Faster arithmetic for
+// number-theoretic transforms", J. Symb. Comp. 2014): inputs and outputs in
+// [0, 4q), twiddle w < q in Montgomery form, q2 = 2q.
+//   x <- x mod 2q;  t <- w*y in [0, 2q);  x' = x + t;  y' = x - t + 2q.
+// Same residues as (x + wy, x - wy) mod q; 5L add-class ops instead of 8L.
+template <int L>
+__device__ __forceinline__ void ct_butterfly_lazy(u32* x, u32* y, const u32* w, const u32* q, const u32* q2,
+                                                  u32 qinv) {
+  u32 xr[L], t[L], d[L];
+  reduce_once<L>(xr, x, q2);
+  mont_mul_lazy<L>(t, y, w, q, qinv);
+  add_vv<L>(x, xr, t);
+  sub_vv<L>(d, xr, t);
+  add_vs<L>(y, d, q2);
 }
 
 // Barrett constants for r = a*b mod q, following Listings 1 and 4 generalised to

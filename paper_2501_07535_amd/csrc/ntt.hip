@@ -15,11 +15,15 @@
 //     level-K block and an offset.  A tile is C groups whose addresses are
 //     consecutive (C >= 16 words per limb plane per row), so global loads and
 //     stores are coalesced in every pass.
+//   * Inside a tile, each thread runs radix-2^r units in registers: 2^r
+//     elements spanning r consecutive stages, so LDS is read and written, and
+//     the workgroup synchronised, once per r stages instead of once per stage.
 //   * Twiddle table: entry m + i' (m = 2^s) holds w_{2m}^{i'} in Montgomery form
 //     (level s stores the first m powers of w_{2m}).  With that order the C
 //     groups of a tile read C consecutive entries, and the first pass reads a
 //     table prefix shared by every tile.
-// Every butterfly is one mont_mul (V*W), one mod_add and one mod_sub.
+// Butterflies use lazy reduction: values stay in [0, 4q) between stages and
+// between passes, and the last pass stores canonical residues in [0, q).
 #include "common.hpp"
 #include "limb.hpp"
 
@@ -28,6 +32,7 @@ namespace moma {
 template <int L>
 struct NttC {
   u32 q[L];
+  u32 q2[L];      // 2q
   u32 qinv;
   u32 nscale[L];  // n^-1 in Montgomery form (inverse transform, last pass)
 };
@@ -60,108 +65,154 @@ __device__ __forceinline__ void load_entry(u32* r, const u32* __restrict__ p) {
   }
 }
 
+// Tile geometry shared by the load, compute and store phases.
+struct TileGeo {
+  u32 k, logc, K, rows, C, E;
+  u64 n, S, o0, ro, b0;
+};
+
+// twiddle table position for local stage sg, local block lb of group g
+__device__ __forceinline__ u64 tw_pos(const TileGeo& t, u32 sg, u32 lb, u32 g) {
+  return (t.K == 0) ? ((1ull << sg) + rev_bits(lb, sg))
+                    : ((1ull << (t.K + sg)) + ((u64)rev_bits(lb, sg) << t.K) + t.b0 + g);
+}
+
+// One round of R stages [sg0, sg0+R) on every radix-2^R unit of the tile.
+template <int L, int R>
+__device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, const u32* __restrict__ tw,
+                                          const NttC<L>& c) {
+  const u32 k = t.k;
+  const u32 B = 1u << (k - sg0);        // block size (rows) at stage sg0
+  const u32 sub = B >> R;                // row spacing of a unit's elements
+  const u32 units = (t.E >> R);
+  for (u32 b = threadIdx.x; b < units; b += blockDim.x) {
+    u32 g = b & (t.C - 1), v = b >> t.logc;
+    u32 lb = v >> (k - sg0 - R);
+    u32 p0 = lb * B + (v & (sub - 1));
+    u32 x[1 << R][L];
+#pragma unroll
+    for (int e = 0; e < (1 << R); e++)
+#pragma unroll
+      for (int j = 0; j < L; j++) x[e][j] = lds[(j * t.rows + p0 + e * sub) * t.C + g];
+#pragma unroll
+    for (int s = 0; s < R; s++) {
+      const int half = 1 << (R - 1 - s);
+#pragma unroll
+      for (int e = 0; e < (1 << R); e++) {
+        if (e & half) continue;
+        u32 lbk = (lb << s) + (u32)(e >> (R - s));
+        u32 w[L];
+        load_entry<L>(w, tw + tw_pos(t, sg0 + s, lbk, g) * L);
+        ct_butterfly_lazy<L>(x[e], x[e + half], w, c.q, c.q2, c.qinv);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < (1 << R); e++)
+#pragma unroll
+      for (int j = 0; j < L; j++) lds[(j * t.rows + p0 + e * sub) * t.C + g] = x[e][j];
+  }
+}
+
+// Workgroup size cap per instantiation: a radix-2^R unit keeps 2^R elements of
+// L limbs live, so wider units get fewer threads and more VGPRs per lane.
+template <int L, int R>
+struct PassTraits {
+  static constexpr int live = L << R;
+  static constexpr int max_threads = live <= 16 ? 1024 : (live <= 32 ? 512 : 256);
+};
+
 // One pass: stages [K, K+k) on tiles of C = 2^logc groups of 2^k elements.
 // LDS holds the tile limb-planar: word (j * 2^k + u) * C + g is limb j of row u
 // of group g, so lanes with consecutive g touch consecutive banks.
-template <int L>
-__global__ __launch_bounds__(256) void ntt_pass_kernel(NttPassArgs a, NttC<L> c) {
+template <int L, int R>
+__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a, NttC<L> c) {
   extern __shared__ u32 lds[];
-  const u32 k = a.k, logc = a.logc, K = a.K;
-  const u32 C = 1u << logc;
-  const u32 rows = 1u << k;
-  const u32 E = rows << logc;
-  const u64 n = a.n;
-  const u32 T = blockDim.x;
-  const u32 tid = threadIdx.x;
+  TileGeo t;
+  t.k = a.k;
+  t.logc = a.logc;
+  t.K = a.K;
+  t.C = 1u << t.logc;
+  t.rows = 1u << t.k;
+  t.E = t.rows << t.logc;
+  t.n = a.n;
+  t.S = t.n >> (t.K + t.k);
   const u64 tile = blockIdx.x;
-
-  // tile -> (base address, first group); see the file comment for the layout
-  u64 o0 = 0, ro = 0, b0 = 0;
-  u64 S = n >> (K + k);
-  if (K == 0) {
-    o0 = tile << logc;
+  t.o0 = t.ro = t.b0 = 0;
+  if (t.K == 0) {
+    t.o0 = tile << t.logc;
   } else {
-    u64 per = (1ull << K) >> logc;
-    ro = tile / per;
-    b0 = (tile % per) << logc;
+    u64 per = (1ull << t.K) >> t.logc;
+    t.ro = tile / per;
+    t.b0 = (tile % per) << t.logc;
   }
+  const u32 tid = threadIdx.x, T = blockDim.x;
+  const u64 n = t.n;
 
-  // ---- load
-  for (u32 e = tid; e < E; e += T) {
-    u32 g = e & (C - 1), v = e >> logc;
+  // ---- load (natural order in the first pass, bit-reversed storage after)
+  for (u32 e = tid; e < t.E; e += T) {
+    u32 g = e & (t.C - 1), v = e >> t.logc;
     u64 src;
     u32 u;
-    if (K == 0) {
+    if (t.K == 0) {
       u = v;
-      src = (u64)u * S + o0 + g;
+      src = (u64)u * t.S + t.o0 + g;
     } else {
-      u = rev_bits(v, k);
-      src = (ro << (K + k)) + ((u64)v << K) + b0 + g;
+      u = rev_bits(v, t.k);
+      src = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
     }
 #pragma unroll
-    for (int j = 0; j < L; j++) lds[(j * rows + u) * C + g] = a.in[(u64)j * n + src];
+    for (int j = 0; j < L; j++) lds[(j * t.rows + u) * t.C + g] = a.in[(u64)j * n + src];
   }
   __syncthreads();
 
-  // ---- stages
-  for (u32 sg = 0; sg < k; sg++) {
-    const u32 hb = k - sg - 1;
-    const u32 h = 1u << hb;
-    for (u32 b = tid; b < (E >> 1); b += T) {
-      u32 g = b & (C - 1), r = b >> logc;
-      u32 lb = r >> hb, pos = r & (h - 1);
-      u32 u1 = (lb << (hb + 1)) + pos, u2 = u1 + h;
-      u64 twpos = (K == 0) ? ((1ull << sg) + rev_bits(lb, sg))
-                           : ((1ull << (K + sg)) + ((u64)rev_bits(lb, sg) << K) + b0 + g);
-      u32 w[L], x[L], y[L], t[L];
-      load_entry<L>(w, a.tw + twpos * L);
-#pragma unroll
-      for (int j = 0; j < L; j++) {
-        x[j] = lds[(j * rows + u1) * C + g];
-        y[j] = lds[(j * rows + u2) * C + g];
-      }
-      mont_mul<L>(t, y, w, c.q, c.qinv);
-      u32 s0[L], s1[L];
-      mod_add<L>(s0, x, t, c.q);
-      mod_sub<L>(s1, x, t, c.q);
-#pragma unroll
-      for (int j = 0; j < L; j++) {
-        lds[(j * rows + u1) * C + g] = s0[j];
-        lds[(j * rows + u2) * C + g] = s1[j];
-      }
+  // ---- stages, R at a time in registers
+  u32 sg = 0;
+  while (sg < t.k) {
+    u32 rem = t.k - sg;
+    if (R >= 3 && rem >= 3) {
+      ntt_round<L, (R >= 3 ? 3 : 1)>(lds, t, sg, a.tw, c);
+      sg += (R >= 3 ? 3 : 1);
+    } else if (R >= 2 && rem >= 2) {
+      ntt_round<L, (R >= 2 ? 2 : 1)>(lds, t, sg, a.tw, c);
+      sg += (R >= 2 ? 2 : 1);
+    } else {
+      ntt_round<L, 1>(lds, t, sg, a.tw, c);
+      sg += 1;
     }
     __syncthreads();
   }
 
   // ---- store
   const u32 logn = a.logn;
-  for (u32 e = tid; e < E; e += T) {
+  for (u32 e = tid; e < t.E; e += T) {
     u32 g, v, u;
     u64 dst;
-    if (K == 0) {
+    if (t.K == 0) {
       // consecutive lanes write consecutive addresses inside one group's run
-      g = e >> k;
-      v = e & (rows - 1);
-      u = rev_bits(v, k);
-      dst = ((u64)rev_bits((u32)(o0 + g), logn - k) << k) + v;
+      g = e >> t.k;
+      v = e & (t.rows - 1);
+      u = rev_bits(v, t.k);
+      dst = ((u64)rev_bits((u32)(t.o0 + g), logn - t.k) << t.k) + v;
     } else {
-      g = e & (C - 1);
-      v = e >> logc;
-      u = rev_bits(v, k);
-      dst = (ro << (K + k)) + ((u64)v << K) + b0 + g;
+      g = e & (t.C - 1);
+      v = e >> t.logc;
+      u = rev_bits(v, t.k);
+      dst = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
     }
     u32 x[L];
 #pragma unroll
-    for (int j = 0; j < L; j++) x[j] = lds[(j * rows + u) * C + g];
-    if (a.scale) {
-      u32 s[L];
-      mont_mul<L>(s, x, c.nscale, c.q, c.qinv);
-#pragma unroll
-      for (int j = 0; j < L; j++) a.out[(u64)j * n + dst] = s[j];
-    } else {
-#pragma unroll
-      for (int j = 0; j < L; j++) a.out[(u64)j * n + dst] = x[j];
+    for (int j = 0; j < L; j++) x[j] = lds[(j * t.rows + u) * t.C + g];
+    if (a.last) {
+      u32 y[L];
+      if (a.scale) {
+        mont_mul_lazy<L>(y, x, c.nscale, c.q, c.qinv);  // x < 4q, nscale < q: y in [0, 2q)
+      } else {
+        reduce_once<L>(y, x, c.q2);                      // [0, 4q) -> [0, 2q)
+      }
+      reduce_once<L>(x, y, c.q);                         // -> [0, q)
     }
+#pragma unroll
+    for (int j = 0; j < L; j++) a.out[(u64)j * n + dst] = x[j];
   }
 }
 
@@ -196,39 +247,59 @@ __global__ __launch_bounds__(256) void twiddle_kernel(u32* __restrict__ tw, u64 
   for (int j = 0; j < L; j++) tw[e * L + j] = acc[j];
 }
 
-uint32_t ntt_tile_elems(int L) {
-  // 64 KiB of LDS per tile keeps two or more workgroups resident per CU
-  uint32_t words = 16384u / (uint32_t)L;
-  uint32_t e = 1;
-  while (e * 2 <= words) e *= 2;
-  return e;
-}
-
 template <int L>
 static NttC<L> make_consts(const FieldRaw& f, const NttConsts* nc) {
   NttC<L> c;
+  u64 carry = 0;
   for (int j = 0; j < L; j++) {
     c.q[j] = f.q[j];
+    u64 d = ((u64)f.q[j] << 1) + carry;  // 2q limb by limb (q < 2^(32L-4): no overflow)
+    c.q2[j] = (u32)d;
+    carry = d >> 32;
     c.nscale[j] = nc ? nc->nscale_m[j] : 0;
   }
   c.qinv = f.qinv;
   return c;
 }
 
-template <int L>
-static int launch_pass_L(const FieldRaw& f, const NttPassArgs& a, const NttConsts& nc, uint32_t threads,
-                         uint64_t tiles, hipStream_t s) {
-  NttC<L> c = make_consts<L>(f, &nc);
+template <int L, int R>
+static int launch_pass_LR(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
   size_t lds = (size_t)L * ((size_t)1 << (a.k + a.logc)) * sizeof(u32);
-  hipLaunchKernelGGL((ntt_pass_kernel<L>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
+  static bool attr_set = false;
+  if (lds > 65536 && !attr_set) {
+    (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((ntt_pass_kernel<L, R>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
   return (int)hipGetLastError();
 }
 
+template <int L>
+static int launch_pass_L(const FieldRaw& f, const NttPassArgs& a, const NttConsts& nc, uint32_t threads,
+                         uint64_t tiles, uint32_t radix_log, hipStream_t s) {
+  NttC<L> c = make_consts<L>(f, &nc);
+  // register blocking is limited by the VGPR budget: 2^r elements of L limbs
+  if (radix_log == 1) return launch_pass_LR<L, 1>(c, a, threads, tiles, s);
+  if constexpr (L <= kMaxLimbsRadix4) {
+    if (radix_log == 2) return launch_pass_LR<L, 2>(c, a, threads, tiles, s);
+  }
+  if constexpr (L <= kMaxLimbsRadix8) {
+    if (radix_log == 3) return launch_pass_LR<L, 3>(c, a, threads, tiles, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+uint32_t ntt_max_threads(int L, uint32_t radix_log) {
+  int live = L << radix_log;
+  return live <= 16 ? 1024u : (live <= 32 ? 512u : 256u);
+}
+
 int launch_ntt_pass(const FieldRaw& f, const NttPassArgs& a, const NttConsts& c, uint32_t threads, uint64_t tiles,
-                    hipStream_t s) {
+                    uint32_t radix_log, hipStream_t s) {
   switch (f.L) {
 #define CASE(LL) \
-  case LL: return launch_pass_L<LL>(f, a, c, threads, tiles, s);
+  case LL: return launch_pass_L<LL>(f, a, c, threads, tiles, radix_log, s);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }
