@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--logn", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--batch-jobs", type=int, default=4096)
+    ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
 
 
@@ -126,6 +129,10 @@ def main():
     achieved = ops / launches / (launch_ms * 1e-3) / 1e12
     peak = PEAK_INT_OPS / 1e12
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_vs_plain(args.batch_jobs, args.batch_reps)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(q, L, w, x, n, logn, args.cpu_seconds)
@@ -157,9 +164,74 @@ def main():
                    "ns_per_butterfly_paper_metric": round(2 * ms_step * 1e6 / (n * logn), 6),
                    "hbm_bytes_min_per_step": 2 * n * 4 * L,
                    "roundtrip_exact": roundtrip, "sampled_vs_oracle": sampled_ok,
-                   "batched_vs_plain_speedup": None},
+                   "batched_vs_plain_speedup": batch["speedup"] if batch else None,
+                   "batch": batch},
     }
     print(json.dumps(rec), flush=True)
+
+
+def batch_vs_plain(njobs: int, reps: int):
+    """The batched workload: njobs transforms, log2 n uniform in 10..16, widths
+    {64,128,256,384} bits, each with its own prime.  Plain = one moma_ntt_fwd C
+    call per job on one stream (arguments prebuilt, so the loop is the library's
+    own per-call cost); batched = one moma_batch_run (one graph launch).  Both
+    timed with events on the stream, plans built beforehand."""
+    import ctypes
+
+    import torch
+
+    import paper_2501_07535_amd as moma
+    jobs = mi.batch_jobs(njobs)
+    xs = mi.batch_inputs(jobs)
+    dev = torch.device("cuda:0")
+    dx = [torch.from_numpy(mi.to_planar(x).view(np.int32)).to(dev) for x in xs]
+    del xs
+    outs_plain = [torch.empty_like(x) for x in dx]
+    outs_batch = [torch.empty_like(x) for x in dx]
+    lib = moma.library()
+    args = []
+    for j, x, o in zip(jobs, dx, outs_plain):
+        L = j.limbs
+        qw, ww = moma._words(j.field.q, L), moma._words(j.omega, L)
+        moma.ntt_prepare(j.field.q, j.omega, j.n, L)
+        args.append((qw, ww, j.n, L, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(o.data_ptr())))
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    fwd = lib.moma_ntt_fwd
+
+    def plain():
+        for a in args:
+            rc = fwd(a[0], a[1], a[2], a[3], a[4], a[5], sp)
+            if rc:
+                raise moma.MomaError(rc)
+
+    t0 = time.perf_counter()
+    b = moma.Batch([(x, o, j.field.q, j.omega, False) for j, x, o in zip(jobs, dx, outs_batch)])
+    t_create = time.perf_counter() - t0
+    plain()
+    b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plain()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        b.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / reps
+    same = all(torch.equal(p, q) for p, q in zip(outs_plain, outs_batch))
+    bfly = sum(j.n // 2 * j.logn for j in jobs)
+    info = b.info()
+    b.close()
+    return {"jobs": njobs, "plain_ms": round(t_plain, 4), "batched_ms": round(t_batch, 4),
+            "speedup": round(t_plain / t_batch, 3), "batched_gbutterfly_s": round(bfly / (t_batch * 1e-3) / 1e9, 3),
+            "graph_launches": info["launches"], "tiles": info["items"], "create_s": round(t_create, 2),
+            "outputs_identical": same}
 
 
 def cpu_baseline(q, L, w, x, n, logn, seconds):

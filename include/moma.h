@@ -147,6 +147,39 @@ int moma_ntt_set_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, 
 int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
                           moma_ntt_schedule_t* sched);
 
+/*
+ * Batched transforms (the paper batches kernels to fill the GPU, Section 5.1):
+ * many NTTs of different sizes, limb counts and moduli run as one hipGraph
+ * launch.  A job is one transform of the kind moma_ntt_fwd / moma_ntt_inv run,
+ * with the same argument meanings and preconditions; its plan is built (and
+ * shared with identical jobs) by moma_batch_create.  The batch keeps the job
+ * buffers' addresses: they must stay allocated, and are read and written by
+ * every moma_batch_run.  Each job's output equals what the plain call with the
+ * same arguments produces, bit for bit.  Jobs must not overlap one another's
+ * output buffers.
+ */
+typedef struct moma_ntt_job {
+  const uint32_t* q;      /* host, limbs words */
+  const uint32_t* omega;  /* host, limbs words: forward primitive n-th root */
+  uint64_t n;
+  uint32_t limbs;
+  uint32_t inverse;       /* 0 forward, 1 inverse */
+  const uint32_t* d_in;   /* device, limb-planar */
+  uint32_t* d_out;        /* device, limb-planar; may equal d_in */
+} moma_ntt_job_t;
+
+typedef struct moma_batch* moma_batch_t;
+
+/* Validate the jobs, build their plans and capture the batch into a graph.
+ * Synchronises the device.  *out is NULL on failure. */
+int moma_batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, moma_batch_t* out);
+/* Enqueue the whole batch on `stream` as one graph launch. */
+int moma_batch_run(moma_batch_t batch, void* stream);
+/* Kernel launches inside the graph and work items (tiles) they cover. */
+int moma_batch_info(moma_batch_t batch, uint32_t* launches, uint64_t* items);
+/* Release the graph and the batch's tables (plans stay cached). */
+int moma_batch_destroy(moma_batch_t batch);
+
 /* Free every cached plan and device table.  Safe to call more than once. */
 void moma_shutdown(void);
 

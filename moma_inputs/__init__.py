@@ -337,3 +337,60 @@ def log2_exact(n: int) -> int:
     if n <= 0 or (1 << k) != n:
         raise ValueError(f"{n} is not a power of two")
     return k
+
+
+# ----------------------------------------------------------------------------- batched workload
+
+BATCH_WIDTHS = (64, 128, 256, 384)
+BATCH_LOGN = tuple(range(10, 17))
+
+
+@dataclass(frozen=True)
+class BatchJob:
+    index: int
+    lam: int
+    logn: int
+    field: Field
+
+    @property
+    def n(self) -> int:
+        return 1 << self.logn
+
+    @property
+    def limbs(self) -> int:
+        return self.field.limbs
+
+    @property
+    def omega(self) -> int:
+        return self.field.root(self.n)
+
+
+def batch_shape(index: int, config: int = 3) -> tuple[int, int]:
+    """(bit-width class, log2 n) of job `index`: the class uniform over
+    {64, 128, 256, 384} and log2 n uniform over the integers 10..16."""
+    r = splitmix64_scalar(stream_key(P_JOBS, config), index)
+    lam = BATCH_WIDTHS[(r & 0xFFFF) % len(BATCH_WIDTHS)]
+    logn = BATCH_LOGN[((r >> 16) & 0xFFFF) % len(BATCH_LOGN)]
+    return lam, logn
+
+
+def _make_job(args):
+    index, config = args
+    lam, logn = batch_shape(index, config)
+    return BatchJob(index=index, lam=lam, logn=logn, field=find_prime(lam, config, index))
+
+
+def batch_jobs(count: int, config: int = 3, workers: int | None = None) -> list[BatchJob]:
+    """`count` jobs of the batched workload, each with its own seeded prime."""
+    work = [(i, config) for i in range(count)]
+    if count < 64:
+        return [_make_job(w) for w in work]
+    from concurrent.futures import ProcessPoolExecutor
+    nw = workers or max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=nw) as ex:
+        return list(ex.map(_make_job, work, chunksize=32))
+
+
+def batch_inputs(jobs: list[BatchJob], config: int = 3) -> list[np.ndarray]:
+    """Uniform residues for each job, element-major (n, L)."""
+    return [residues(j.field, j.n, j.limbs, config, 1000 + j.index) for j in jobs]

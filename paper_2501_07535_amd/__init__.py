@@ -74,6 +74,21 @@ _lib.moma_ntt_set_schedule.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_u
 _lib.moma_ntt_set_schedule.restype = ctypes.c_int
 _lib.moma_ntt_get_schedule.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Schedule)]
 _lib.moma_ntt_get_schedule.restype = ctypes.c_int
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("q", _u32p), ("omega", _u32p), ("n", ctypes.c_uint64), ("limbs", ctypes.c_uint32),
+                ("inverse", ctypes.c_uint32), ("d_in", _vp), ("d_out", _vp)]
+
+
+_lib.moma_batch_create.argtypes = [ctypes.POINTER(_Job), ctypes.c_uint32, ctypes.POINTER(_vp)]
+_lib.moma_batch_create.restype = ctypes.c_int
+_lib.moma_batch_run.argtypes = [_vp, _vp]
+_lib.moma_batch_run.restype = ctypes.c_int
+_lib.moma_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]
+_lib.moma_batch_info.restype = ctypes.c_int
+_lib.moma_batch_destroy.argtypes = [_vp]
+_lib.moma_batch_destroy.restype = ctypes.c_int
 _lib.moma_strerror.argtypes = [ctypes.c_int]
 _lib.moma_strerror.restype = ctypes.c_char_p
 _lib.moma_last_error_detail.restype = ctypes.c_char_p
@@ -84,7 +99,8 @@ MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA
 
 EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
             "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_prepare", "moma_ntt_describe",
-            "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_shutdown")
+            "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_batch_create", "moma_batch_run",
+            "moma_batch_info", "moma_batch_destroy", "moma_shutdown")
 
 
 class MomaError(RuntimeError):
@@ -228,6 +244,47 @@ def ntt_get_schedule(q: int, omega: int, n: int, limbs: int) -> tuple:
     s = Schedule()
     _check(_lib.moma_ntt_get_schedule(_words(q, limbs), _words(omega, limbs), n, limbs, ctypes.byref(s)))
     return s.as_tuple()
+
+
+class Batch:
+    """Many transforms run as one graph launch.
+
+    jobs: iterable of (x, out, q, omega, inverse) with x / out limb-planar device
+    tensors of shape (limbs, n) (out may be x).  The batch keeps references to
+    the tensors; run() recomputes every job from its current input.
+    """
+
+    def __init__(self, jobs):
+        self._keep = []
+        recs = []
+        for x, out, q, omega, inverse in jobs:
+            _dev(x, "x")
+            _dev(out, "out")
+            limbs, n = x.shape
+            qw, ww = _words(q, limbs), _words(omega, limbs)
+            self._keep += [x, out, qw, ww]
+            recs.append(_Job(ctypes.cast(qw, _u32p), ctypes.cast(ww, _u32p), n, limbs, 1 if inverse else 0,
+                             x.data_ptr(), out.data_ptr()))
+        arr = (_Job * len(recs))(*recs)
+        h = _vp()
+        _check(_lib.moma_batch_create(arr, len(recs), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_lib.moma_batch_run(self._h, _stream(stream)))
+
+    def info(self) -> dict:
+        nl, ni = ctypes.c_uint32(0), ctypes.c_uint64(0)
+        _check(_lib.moma_batch_info(self._h, ctypes.byref(nl), ctypes.byref(ni)))
+        return {"launches": int(nl.value), "items": int(ni.value)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.moma_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def shutdown():

@@ -14,35 +14,28 @@
 #include "../../include/moma.h"
 #include "common.hpp"
 #include "hostbig.hpp"
+#include "plan.hpp"
 
 namespace moma {
 
-static thread_local std::string g_detail;
+thread_local std::string g_detail;
 
 int set_error(int code, const std::string& detail) {
   g_detail = detail;
   return code;
 }
 
-static int hip_fail(int e, const char* what) {
+int hip_fail(int e, const char* what) {
   if (e == 0) return MOMA_OK;
   return set_error(MOMA_E_HIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e));
 }
 
 // ------------------------------------------------------------------ fields
 
-struct FieldEntry {
-  FieldRaw f;
-  HBig Q, one_m;
-  // last axpy scalar, cached with its Montgomery form
-  std::vector<uint32_t> alpha_key;
-  std::vector<uint32_t> alpha_m;
-};
-
-static std::mutex g_mu;
+std::mutex g_mu;
 static std::map<std::vector<uint32_t>, std::shared_ptr<FieldEntry>> g_fields;
 
-static int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* out) {
+int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* out) {
   if (!q) return set_error(MOMA_E_ARG, "q is NULL");
   if (limbs < MOMA_MIN_LIMBS || limbs > MOMA_MAX_LIMBS)
     return set_error(MOMA_E_ARG, "limbs must be in [2, 32], got " + std::to_string(limbs));
@@ -94,40 +87,15 @@ static int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldE
 
 // ------------------------------------------------------------------ transform plans
 
-struct DirTables {
-  uint32_t* tw = nullptr;      // n entries x L words, Montgomery form
-  uint32_t* ladder = nullptr;  // (logn + 1) x L words: w^(2^b) in Montgomery form, then 1
-};
-
-struct NttPlan {
-  std::shared_ptr<FieldEntry> fe;
-  int device = 0;
-  uint64_t n = 0;
-  uint32_t logn = 0;
-  DirTables fwd, inv;
-  NttConsts inv_consts;
-  uint32_t* scratch = nullptr;  // for in-place multi-pass calls
-  NttSchedule sched;
-  std::vector<NttPass> passes;
-  std::mutex mu;  // guards scratch allocation and schedule changes
-  ~NttPlan() {
-    (void)hipFree(fwd.tw);
-    (void)hipFree(fwd.ladder);
-    (void)hipFree(inv.tw);
-    (void)hipFree(inv.ladder);
-    (void)hipFree(scratch);
-  }
-};
-
 static std::map<std::vector<uint32_t>, std::shared_ptr<NttPlan>> g_plans;
 
-static uint32_t max_radix_log(int L) {
+uint32_t max_radix_log(int L) {
   return L <= kMaxLimbsRadix8 ? 3u : (L <= kMaxLimbsRadix4 ? 2u : 1u);
 }
 
 // Split log2 n stages into passes for a schedule; returns MOMA_OK or an error
 // code when the schedule cannot run this size.
-static int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out) {
+int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out) {
   if (s.threads < 64 || s.threads > 1024 || s.threads % 64)
     return set_error(MOMA_E_ARG, "threads must be a multiple of 64 in [64, 1024]");
   if (s.radix_log < 1 || s.radix_log > max_radix_log(L))
@@ -164,7 +132,7 @@ static int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<N
 // fits a 64 KiB tile; otherwise 32 KiB tiles (several workgroups per CU) with
 // 16, 8 or 4 coalesced columns.  Radix-4 register units where the VGPR budget
 // allows, and enough threads to give each one or two units per round.
-static NttSchedule default_schedule(int L, uint32_t logn) {
+NttSchedule default_schedule(int L, uint32_t logn) {
   auto lg = [](uint32_t words) {
     uint32_t t = 0;
     while ((2u << t) <= words) t++;
@@ -227,8 +195,7 @@ static int build_tables(NttPlan& p, const HBig& w, DirTables* t) {
   return MOMA_OK;
 }
 
-static int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
-                    std::shared_ptr<NttPlan>* out) {
+int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, std::shared_ptr<NttPlan>* out) {
   if (!omega) return set_error(MOMA_E_ARG, "omega is NULL");
   if (n < 2 || (n & (n - 1)) || n > (1ull << MOMA_MAX_LOG_N))
     return set_error(MOMA_E_ARG, "n must be a power of two in [2, 2^26], got " + std::to_string(n));

@@ -70,6 +70,13 @@ int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s);
 int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, hipStream_t s);
 int launch_ntt_pass(const FieldRaw& f, const NttPassArgs& a, const NttConsts& c, uint32_t threads, uint64_t tiles,
                     uint32_t radix_log, hipStream_t s);
+// batched transforms: one launch runs items (pass record, tile) of many plans
+size_t ntt_consts_bytes(int L);
+void ntt_batch_prepare(int L, uint32_t radix_log, size_t lds);
+void ntt_fill_consts(const FieldRaw& f, const NttConsts* nc, void* dst);
+int launch_ntt_batch(int L, uint32_t radix_log, uint32_t threads, size_t lds, uint32_t grid,
+                     const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
+                     hipStream_t s);
 // largest workgroup the pass kernel for (L, radix_log) was compiled for
 uint32_t ntt_max_threads(int L, uint32_t radix_log);
 int launch_twiddle_gen(const FieldRaw& f, uint32_t* tw, uint64_t n, uint32_t logn, const uint32_t* d_ladder,

@@ -24,6 +24,8 @@
 //     table prefix shared by every tile.
 // Butterflies use lazy reduction: values stay in [0, 4q) between stages and
 // between passes, and the last pass stores canonical residues in [0, q).
+#include <string.h>
+
 #include "common.hpp"
 #include "limb.hpp"
 
@@ -113,20 +115,12 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
   }
 }
 
-// Workgroup size cap per instantiation: a radix-2^R unit keeps 2^R elements of
-// L limbs live, so wider units get fewer threads and more VGPRs per lane.
-template <int L, int R>
-struct PassTraits {
-  static constexpr int live = L << R;
-  static constexpr int max_threads = live <= 16 ? 1024 : (live <= 32 ? 512 : 256);
-};
 
-// One pass: stages [K, K+k) on tiles of C = 2^logc groups of 2^k elements.
+// One tile of one pass: stages [K, K+k) on C = 2^logc groups of 2^k elements.
 // LDS holds the tile limb-planar: word (j * 2^k + u) * C + g is limb j of row u
 // of group g, so lanes with consecutive g touch consecutive banks.
 template <int L, int R>
-__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a, NttC<L> c) {
-  extern __shared__ u32 lds[];
+__device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const NttC<L>& c, u64 tile) {
   TileGeo t;
   t.k = a.k;
   t.logc = a.logc;
@@ -136,7 +130,6 @@ __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kern
   t.E = t.rows << t.logc;
   t.n = a.n;
   t.S = t.n >> (t.K + t.k);
-  const u64 tile = blockIdx.x;
   t.o0 = t.ro = t.b0 = 0;
   if (t.K == 0) {
     t.o0 = tile << t.logc;
@@ -213,6 +206,38 @@ __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kern
     }
 #pragma unroll
     for (int j = 0; j < L; j++) a.out[(u64)j * n + dst] = x[j];
+  }
+}
+
+// Workgroup size cap per instantiation: a radix-2^R unit keeps 2^R elements of
+// L limbs live, so wider units get fewer threads and more VGPRs per lane.
+template <int L, int R>
+struct PassTraits {
+  static constexpr int live = L << R;
+  static constexpr int max_threads = live <= 16 ? 1024 : (live <= 32 ? 512 : 256);
+};
+
+// One pass of one transform: workgroup b runs tile b.
+template <int L, int R>
+__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a, NttC<L> c) {
+  extern __shared__ u32 lds[];
+  pass_tile<L, R>(lds, a, c, blockIdx.x);
+}
+
+// One phase of a batch: items[i] = (pass record, tile); every pass record names
+// its own transform (buffers, size, stages, twiddles) and its modulus constants.
+// Items are sorted by decreasing cost and dealt round-robin to a fixed grid.
+template <int L, int R>
+__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_kernel(
+    const NttPassArgs* __restrict__ passes, const NttC<L>* __restrict__ consts, const uint2* __restrict__ items,
+    u32 nitems) {
+  extern __shared__ u32 lds[];
+  for (u32 i = blockIdx.x; i < nitems; i += gridDim.x) {
+    uint2 it = items[i];
+    const NttPassArgs a = passes[it.x];
+    const NttC<L> c = consts[it.x];
+    pass_tile<L, R>(lds, a, c, it.y);
+    __syncthreads();
   }
 }
 
@@ -304,6 +329,92 @@ int launch_ntt_pass(const FieldRaw& f, const NttPassArgs& a, const NttConsts& c,
 #undef CASE
   }
   return (int)hipErrorInvalidValue;
+}
+
+template <int L, int R>
+static int launch_batch_LR(uint32_t threads, size_t lds, uint32_t grid, const NttPassArgs* d_passes,
+                           const void* d_consts, const uint2* d_items, uint32_t nitems, hipStream_t s) {
+  hipLaunchKernelGGL((ntt_batch_kernel<L, R>), dim3(grid), dim3(threads), lds, s, d_passes,
+                     (const NttC<L>*)d_consts, d_items, nitems);
+  return (int)hipGetLastError();
+}
+
+template <int L>
+static int launch_batch_L(uint32_t radix_log, uint32_t threads, size_t lds, uint32_t grid,
+                          const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
+                          hipStream_t s) {
+  if (radix_log == 1) return launch_batch_LR<L, 1>(threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  if constexpr (L <= kMaxLimbsRadix4) {
+    if (radix_log == 2) return launch_batch_LR<L, 2>(threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  }
+  if constexpr (L <= kMaxLimbsRadix8) {
+    if (radix_log == 3) return launch_batch_LR<L, 3>(threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_ntt_batch(int L, uint32_t radix_log, uint32_t threads, size_t lds, uint32_t grid,
+                     const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
+                     hipStream_t s) {
+  switch (L) {
+#define CASE(LL) \
+  case LL: return launch_batch_L<LL>(radix_log, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+    MOMA_FOR_EACH_L(CASE)
+#undef CASE
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+// allow the batch kernel more than 64 KiB of dynamic LDS; called before graph
+// capture so that nothing but launches is recorded
+template <int L, int R>
+static void batch_attr_LR() {
+  (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+}
+
+template <int L>
+static void batch_attr_L(uint32_t radix_log) {
+  if (radix_log == 1) batch_attr_LR<L, 1>();
+  if constexpr (L <= kMaxLimbsRadix4) {
+    if (radix_log == 2) batch_attr_LR<L, 2>();
+  }
+  if constexpr (L <= kMaxLimbsRadix8) {
+    if (radix_log == 3) batch_attr_LR<L, 3>();
+  }
+}
+
+void ntt_batch_prepare(int L, uint32_t radix_log, size_t lds) {
+  if (lds <= 65536) return;
+  switch (L) {
+#define CASE(LL) \
+  case LL: batch_attr_L<LL>(radix_log); return;
+    MOMA_FOR_EACH_L(CASE)
+#undef CASE
+  }
+}
+
+size_t ntt_consts_bytes(int L) {
+  switch (L) {
+#define CASE(LL) \
+  case LL: return sizeof(NttC<LL>);
+    MOMA_FOR_EACH_L(CASE)
+#undef CASE
+  }
+  return 0;
+}
+
+void ntt_fill_consts(const FieldRaw& f, const NttConsts* nc, void* dst) {
+  switch (f.L) {
+#define CASE(LL)                                  \
+  case LL: {                                      \
+    NttC<LL> c = make_consts<LL>(f, nc);          \
+    memcpy(dst, &c, sizeof(c));                   \
+    return;                                       \
+  }
+    MOMA_FOR_EACH_L(CASE)
+#undef CASE
+  }
 }
 
 template <int L>

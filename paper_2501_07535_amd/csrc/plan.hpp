@@ -1,0 +1,59 @@
+// plan.hpp - host runtime internals shared by the C ABI, the batch executor and
+// the autotuner: per-modulus constants, transform plans and their schedules.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "hostbig.hpp"
+
+namespace moma {
+
+struct FieldEntry {
+  FieldRaw f;
+  HBig Q, one_m;
+  // last axpy scalar, cached with its Montgomery form
+  std::vector<uint32_t> alpha_key;
+  std::vector<uint32_t> alpha_m;
+};
+
+struct DirTables {
+  uint32_t* tw = nullptr;      // n entries x L words, Montgomery form
+  uint32_t* ladder = nullptr;  // (logn + 1) x L words: w^(2^b) in Montgomery form, then 1
+};
+
+struct NttPlan {
+  std::shared_ptr<FieldEntry> fe;
+  int device = 0;
+  uint64_t n = 0;
+  uint32_t logn = 0;
+  DirTables fwd, inv;
+  NttConsts inv_consts;
+  uint32_t* scratch = nullptr;  // for in-place multi-pass calls
+  NttSchedule sched;
+  std::vector<NttPass> passes;
+  std::mutex mu;  // guards scratch allocation and schedule changes
+  ~NttPlan() {
+    (void)hipFree(fwd.tw);
+    (void)hipFree(fwd.ladder);
+    (void)hipFree(inv.tw);
+    (void)hipFree(inv.ladder);
+    (void)hipFree(scratch);
+  }
+};
+
+extern std::mutex g_mu;              // guards the field and plan caches
+extern thread_local std::string g_detail;
+
+int hip_fail(int e, const char* what);
+int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* out);
+int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, std::shared_ptr<NttPlan>* out);
+uint32_t max_radix_log(int L);
+int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out);
+NttSchedule default_schedule(int L, uint32_t logn);
+
+}  // namespace moma
