@@ -394,3 +394,36 @@ def batch_jobs(count: int, config: int = 3, workers: int | None = None) -> list[
 def batch_inputs(jobs: list[BatchJob], config: int = 3) -> list[np.ndarray]:
     """Uniform residues for each job, element-major (n, L)."""
     return [residues(j.field, j.n, j.limbs, config, 1000 + j.index) for j in jobs]
+
+
+# ----------------------------------------------------------------------------- cost-model inputs
+
+MLP_IN, MLP_H = 6, 64
+MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """He-normal initial weights (N(0, 2/fan_in)), zero biases, flat float64 in the
+    layout W1[64][6], b1, W2[64][64], b2, W3[64], b3.  Normal draws come from
+    SplitMix64 by the Box-Muller transform: u = (top 53 bits + 1) / 2^53,
+    z = sqrt(-2 ln u1) cos(2 pi u2)."""
+    sizes = [(MLP_H * MLP_IN, MLP_IN), (MLP_H, 0), (MLP_H * MLP_H, MLP_H), (MLP_H, 0), (MLP_H, MLP_H), (1, 0)]
+    out = []
+    key = stream_key(P_MLP, seed)
+    pos = 0
+    for count, fan_in in sizes:
+        if fan_in == 0:
+            out.append(np.zeros(count))
+            continue
+        r = splitmix64(key, pos, 2 * count)
+        pos += 2 * count
+        u = ((r >> np.uint64(11)).astype(np.float64) + 1.0) / 2.0 ** 53
+        z = np.sqrt(-2.0 * np.log(u[0::2])) * np.cos(2.0 * np.pi * u[1::2])
+        out.append(z * np.sqrt(2.0 / fan_in))
+    return np.concatenate(out)
+
+
+def uniform01(n: int, *ids: int) -> np.ndarray:
+    """n doubles uniform in (0, 1] from the stream ids (53-bit resolution)."""
+    r = splitmix64(stream_key(*ids), 0, n)
+    return ((r >> np.uint64(11)).astype(np.float64) + 1.0) / 2.0 ** 53

@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc and OpenMP (in place, next to its source)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -58,6 +58,11 @@ def lib():
         L.oracle_mod_pow.argtypes = [_u32p, _u32p, _u32p, ctypes.c_int, _u32p, ctypes.c_int]
         L.oracle_mod_inv.argtypes = [_u32p, _u32p, _u32p, ctypes.c_int]
         L.oracle_addback_count.restype = ctypes.c_int64
+        _dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_mlp_forward.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
+        L.oracle_mlp_grad.argtypes = [_dp, _dp, _dp, ctypes.c_int64, _dp, _dp]
+        L.oracle_mlp_adam.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double]
     return _lib
 
 
@@ -224,3 +229,50 @@ def intt_radix2(q: int, L: int, omega: int, y) -> np.ndarray:
 
 def cyclic_conv(q: int, L: int, a, b) -> np.ndarray:
     return _binop("oracle_cyclic_conv", q, L, a, b)
+
+
+# ----------------------------------------------------------------- MLP (FP64)
+
+MLP_IN, MLP_H = 6, 64
+
+
+def mlp_nparams() -> int:
+    return int(lib().oracle_mlp_nparams())
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def mlp_forward(params, x) -> np.ndarray:
+    """Network output for each row of x (rows x 6)."""
+    p, pp = _d(params)
+    xx, xp = _d(x)
+    y = np.zeros(xx.shape[0])
+    _, yp = _d(y)
+    assert lib().oracle_mlp_forward(pp, xp, xx.shape[0], yp) == 0
+    return y
+
+
+def mlp_grad(params, x, t) -> tuple[np.ndarray, float]:
+    """Gradient of the mean squared error with respect to every parameter, and the loss."""
+    p, pp = _d(params)
+    xx, xp = _d(x)
+    tt, tp = _d(t)
+    g = np.zeros(mlp_nparams())
+    loss = np.zeros(1)
+    _, gp = _d(g)
+    _, lp = _d(loss)
+    assert lib().oracle_mlp_grad(pp, xp, tp, xx.shape[0], gp, lp) == 0
+    return g, float(loss[0])
+
+
+def mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place on params, m, v (float64 arrays)."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g, gp = _d(grad)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib().oracle_mlp_adam(params.ctypes.data_as(dp), gp, m.ctypes.data_as(dp), v.ctypes.data_as(dp), step,
+                                 lr, beta1, beta2, eps) == 0

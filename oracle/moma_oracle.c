@@ -29,6 +29,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -468,6 +469,114 @@ int oracle_cyclic_conv(const limb_t *q, int L, int64_t n, const limb_t *a, const
       memcpy(acc, s, sizeof(limb_t) * (size_t)L);
     }
     memcpy(out + k * L, acc, sizeof(limb_t) * (size_t)L);
+  }
+  return 0;
+}
+
+/* ================================================================== MLP
+ * FP64 reference for the learned schedule cost model: a multilayer perceptron
+ * 6 -> 64 -> 64 -> 1 with ReLU after the two hidden layers, mean squared error
+ * loss, and Adam (Kingma and Ba, ICLR 2015) with bias correction.
+ * Parameters are one flat array:
+ *   W1[64][6], b1[64], W2[64][64], b2[64], W3[64], b3   (4673 values)
+ * with W[o][i] the weight from input i to output o.
+ */
+#define MLP_IN 6
+#define MLP_H 64
+#define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1)
+
+int oracle_mlp_nparams(void) { return MLP_NPARAM; }
+
+static void mlp_views(const double *p, const double **W1, const double **b1, const double **W2, const double **b2,
+                      const double **W3, const double **b3) {
+  *W1 = p;
+  *b1 = *W1 + MLP_H * MLP_IN;
+  *W2 = *b1 + MLP_H;
+  *b2 = *W2 + MLP_H * MLP_H;
+  *W3 = *b2 + MLP_H;
+  *b3 = *W3 + MLP_H;
+}
+
+/* one sample: hidden activations (after ReLU) and output */
+static double mlp_one(const double *p, const double *x, double *h1, double *h2) {
+  const double *W1, *b1, *W2, *b2, *W3, *b3;
+  mlp_views(p, &W1, &b1, &W2, &b2, &W3, &b3);
+  for (int o = 0; o < MLP_H; o++) {
+    double s = b1[o];
+    for (int i = 0; i < MLP_IN; i++) s += W1[o * MLP_IN + i] * x[i];
+    h1[o] = s > 0 ? s : 0;
+  }
+  for (int o = 0; o < MLP_H; o++) {
+    double s = b2[o];
+    for (int i = 0; i < MLP_H; i++) s += W2[o * MLP_H + i] * h1[i];
+    h2[o] = s > 0 ? s : 0;
+  }
+  double y = b3[0];
+  for (int i = 0; i < MLP_H; i++) y += W3[i] * h2[i];
+  return y;
+}
+
+int oracle_mlp_forward(const double *params, const double *x, int64_t rows, double *y) {
+  if (rows < 0) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < rows; r++) {
+    double h1[MLP_H], h2[MLP_H];
+    y[r] = mlp_one(params, x + r * MLP_IN, h1, h2);
+  }
+  return 0;
+}
+
+/* loss = (1/rows) sum (y - t)^2 and its gradient with respect to every parameter
+ * (chain rule through the output layer, the second ReLU layer, the first) */
+int oracle_mlp_grad(const double *params, const double *x, const double *t, int64_t rows, double *grad,
+                    double *loss) {
+  if (rows <= 0) return -1;
+  const double *W1, *b1, *W2, *b2, *W3, *b3;
+  mlp_views(params, &W1, &b1, &W2, &b2, &W3, &b3);
+  memset(grad, 0, sizeof(double) * MLP_NPARAM);
+  double *gW1 = grad, *gb1 = gW1 + MLP_H * MLP_IN, *gW2 = gb1 + MLP_H, *gb2 = gW2 + MLP_H * MLP_H,
+         *gW3 = gb2 + MLP_H, *gb3 = gW3 + MLP_H;
+  double L = 0;
+  for (int64_t r = 0; r < rows; r++) {
+    double h1[MLP_H], h2[MLP_H], d2[MLP_H], d1[MLP_H];
+    const double *xr = x + r * MLP_IN;
+    double y = mlp_one(params, xr, h1, h2);
+    double e = y - t[r];
+    L += e * e;
+    double dy = 2.0 * e / (double)rows;
+    gb3[0] += dy;
+    for (int i = 0; i < MLP_H; i++) {
+      gW3[i] += dy * h2[i];
+      d2[i] = h2[i] > 0 ? dy * W3[i] : 0;
+    }
+    for (int o = 0; o < MLP_H; o++) {
+      gb2[o] += d2[o];
+      for (int i = 0; i < MLP_H; i++) gW2[o * MLP_H + i] += d2[o] * h1[i];
+    }
+    for (int i = 0; i < MLP_H; i++) {
+      double s = 0;
+      for (int o = 0; o < MLP_H; o++) s += W2[o * MLP_H + i] * d2[o];
+      d1[i] = h1[i] > 0 ? s : 0;
+    }
+    for (int o = 0; o < MLP_H; o++) {
+      gb1[o] += d1[o];
+      for (int i = 0; i < MLP_IN; i++) gW1[o * MLP_IN + i] += d1[o] * xr[i];
+    }
+  }
+  *loss = L / (double)rows;
+  return 0;
+}
+
+/* one Adam step, step counter t >= 1:
+ * m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;  p -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps) */
+int oracle_mlp_adam(double *params, const double *grad, double *m, double *v, int64_t t, double lr, double beta1,
+                    double beta2, double eps) {
+  if (t < 1) return -1;
+  double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+  for (int i = 0; i < MLP_NPARAM; i++) {
+    m[i] = beta1 * m[i] + (1.0 - beta1) * grad[i];
+    v[i] = beta2 * v[i] + (1.0 - beta2) * grad[i] * grad[i];
+    params[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
   }
   return 0;
 }
