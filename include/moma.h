@@ -148,6 +148,96 @@ int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, 
                           moma_ntt_schedule_t* sched);
 
 /*
+ * Autotuner.  For one (q, omega, n, limbs) plan: enumerate every launch shape
+ * the kernels can run (moma_ntt_candidates), time each with HIP events
+ * (`warmup` untimed runs, then the median of `reps` repetitions, each long
+ * enough to dwarf event resolution), install the fastest in the plan and
+ * append every measurement to the process's timing database.  With top_k > 0
+ * and a cost model loaded, only the model's top_k shapes are timed (without a
+ * model that returns MOMA_E_UNSUPPORTED).  max_candidates > 0 truncates the
+ * enumeration.  Ties go to the earlier candidate.  Allocates two scratch
+ * transforms and synchronises.
+ */
+typedef struct moma_tune_opts {
+  uint32_t reps;            /* timed repetitions per shape (median), default 5 */
+  uint32_t warmup;          /* untimed runs per shape, default 2 */
+  uint32_t top_k;           /* 0: exhaustive; else time the cost model's top_k */
+  uint32_t max_candidates;  /* 0: no limit */
+} moma_tune_opts_t;
+
+typedef struct moma_tune_result {
+  moma_ntt_schedule_t best;
+  float best_us;            /* median microseconds of one forward transform */
+  uint32_t timed;           /* shapes timed */
+  uint32_t feasible;        /* shapes enumerated */
+} moma_tune_result_t;
+
+int moma_ntt_tune(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const moma_tune_opts_t* opts,
+                  moma_tune_result_t* result);
+/* The feasible shapes for a compute limb count and size, in the tuner's order.
+ * Writes at most `max` entries to out (may be NULL) and the total to *count. */
+int moma_ntt_candidates(uint32_t limbs_compute, uint32_t log2_n, moma_ntt_schedule_t* out, uint32_t max,
+                        uint32_t* count);
+
+/* Timing database: one row per timed shape.  Plans created after a load start
+ * from the fastest recorded shape for their (compute limbs, log2 n) on the
+ * same device name.  CSV: device,limbs,log2_n,tile_log,col_log,threads,
+ * radix_log,us,reps. */
+typedef struct moma_tune_row {
+  uint32_t limbs;           /* compute limbs */
+  uint32_t log2_n;
+  moma_ntt_schedule_t sched;
+  float us;
+  uint32_t reps;
+} moma_tune_row_t;
+uint32_t moma_tune_db_count(void);
+int moma_tune_db_get(uint32_t index, moma_tune_row_t* row);
+void moma_tune_db_clear(void);
+int moma_tune_db_save(const char* path);
+int moma_tune_db_load(const char* path);
+
+/*
+ * Learned cost model: an FP32 perceptron 6 -> 64 -> 64 -> 1 (ReLU) predicting
+ * log(microseconds) of a schedule from six features (moma_costmodel_features:
+ * log2 n, compute limbs, log2 radix, stages fused per pass, log2 threads,
+ * log2 LDS bytes), trained on the GPU by the library's own kernels with Adam
+ * on mean squared error.  Features and targets are z-scored with the training
+ * set's statistics, which are saved with the weights.
+ */
+typedef struct moma_train_opts {
+  uint32_t epochs;          /* default 200 */
+  uint32_t batch;           /* minibatch rows, default 256 */
+  float lr;                 /* Adam step size, default 3e-3 */
+  uint64_t seed;            /* initial weights and minibatch order (SplitMix64) */
+} moma_train_opts_t;
+
+int moma_costmodel_features(uint32_t limbs_compute, uint32_t log2_n, const moma_ntt_schedule_t* sched, float* out6);
+/* Train from host arrays features[rows][6] and targets log_us[rows]; replaces the
+ * current model.  *final_mse (may be NULL) is the training-set mean squared
+ * error in (log us)^2. */
+int moma_costmodel_train(const float* features, const float* log_us, uint32_t rows, const moma_train_opts_t* opts,
+                         float* final_mse);
+/* Predict log(us) for host features[rows][6]. */
+int moma_costmodel_predict(const float* features, uint32_t rows, float* log_us);
+int moma_costmodel_save(const char* path);
+int moma_costmodel_load(const char* path);
+void moma_costmodel_clear(void);
+
+/* The network's kernels on raw device arrays (features already normalised),
+ * for checking them against a reference: parameters are W1[64][6], b1[64],
+ * W2[64][64], b2[64], W3[64], b3 (moma_mlp_nparams() floats).
+ *   forward: y[r] for rows x[r][6];
+ *   grad:    gradient of mean((y - t)^2) into grad[nparams] and the loss into
+ *            *d_loss; allocates a workspace and synchronises `stream`;
+ *   adam:    one bias-corrected Adam step (step >= 1) on params, m, v. */
+uint32_t moma_mlp_nparams(void);
+int moma_mlp_forward(const float* d_params, const float* d_x, uint32_t rows, float* d_y, void* stream);
+int moma_mlp_grad(const float* d_params, const float* d_x, const float* d_t, uint32_t rows, float* d_grad,
+                  float* d_loss, void* stream);
+int moma_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, uint32_t step, float lr, float beta1,
+                  float beta2, float eps, void* stream);
+
+/*
  * Batched transforms (the paper batches kernels to fill the GPU, Section 5.1):
  * many NTTs of different sizes, limb counts and moduli run as one hipGraph
  * launch.  A job is one transform of the kind moma_ntt_fwd / moma_ntt_inv run,

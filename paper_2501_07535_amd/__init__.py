@@ -89,6 +89,49 @@ _lib.moma_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.PO
 _lib.moma_batch_info.restype = ctypes.c_int
 _lib.moma_batch_destroy.argtypes = [_vp]
 _lib.moma_batch_destroy.restype = ctypes.c_int
+
+
+class _TuneOpts(ctypes.Structure):
+    _fields_ = [("reps", ctypes.c_uint32), ("warmup", ctypes.c_uint32), ("top_k", ctypes.c_uint32),
+                ("max_candidates", ctypes.c_uint32)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("best", Schedule), ("best_us", ctypes.c_float), ("timed", ctypes.c_uint32),
+                ("feasible", ctypes.c_uint32)]
+
+
+class _TuneRow(ctypes.Structure):
+    _fields_ = [("limbs", ctypes.c_uint32), ("log2_n", ctypes.c_uint32), ("sched", Schedule), ("us", ctypes.c_float),
+                ("reps", ctypes.c_uint32)]
+
+
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+_fp = ctypes.POINTER(ctypes.c_float)
+_lib.moma_ntt_tune.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(_TuneOpts),
+                               ctypes.POINTER(_TuneResult)]
+_lib.moma_ntt_candidates.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Schedule), ctypes.c_uint32,
+                                     ctypes.POINTER(ctypes.c_uint32)]
+_lib.moma_tune_db_count.restype = ctypes.c_uint32
+_lib.moma_tune_db_get.argtypes = [ctypes.c_uint32, ctypes.POINTER(_TuneRow)]
+_lib.moma_tune_db_clear.restype = None
+_lib.moma_tune_db_save.argtypes = [ctypes.c_char_p]
+_lib.moma_tune_db_load.argtypes = [ctypes.c_char_p]
+_lib.moma_costmodel_features.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Schedule), _fp]
+_lib.moma_costmodel_train.argtypes = [_fp, _fp, ctypes.c_uint32, ctypes.POINTER(_TrainOpts), _fp]
+_lib.moma_costmodel_predict.argtypes = [_fp, ctypes.c_uint32, _fp]
+_lib.moma_costmodel_save.argtypes = [ctypes.c_char_p]
+_lib.moma_costmodel_load.argtypes = [ctypes.c_char_p]
+_lib.moma_costmodel_clear.restype = None
+_lib.moma_mlp_nparams.restype = ctypes.c_uint32
+_lib.moma_mlp_forward.argtypes = [_vp, _vp, ctypes.c_uint32, _vp, _vp]
+_lib.moma_mlp_grad.argtypes = [_vp, _vp, _vp, ctypes.c_uint32, _vp, _vp, _vp]
+_lib.moma_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, _vp]
 _lib.moma_strerror.argtypes = [ctypes.c_int]
 _lib.moma_strerror.restype = ctypes.c_char_p
 _lib.moma_last_error_detail.restype = ctypes.c_char_p
@@ -100,7 +143,11 @@ MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA
 EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
             "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_prepare", "moma_ntt_describe",
             "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_batch_create", "moma_batch_run",
-            "moma_batch_info", "moma_batch_destroy", "moma_shutdown")
+            "moma_batch_info", "moma_batch_destroy", "moma_ntt_tune", "moma_ntt_candidates", "moma_tune_db_count",
+            "moma_tune_db_get", "moma_tune_db_clear", "moma_tune_db_save", "moma_tune_db_load",
+            "moma_costmodel_features", "moma_costmodel_train", "moma_costmodel_predict", "moma_costmodel_save",
+            "moma_costmodel_load", "moma_costmodel_clear", "moma_mlp_nparams", "moma_mlp_forward", "moma_mlp_grad",
+            "moma_mlp_adam", "moma_shutdown")
 
 
 class MomaError(RuntimeError):
@@ -285,6 +332,112 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+# ----------------------------------------------------------------- autotuner
+
+def ntt_tune(q: int, omega: int, n: int, limbs: int, reps: int = 5, warmup: int = 2, top_k: int = 0,
+             max_candidates: int = 0) -> dict:
+    """Time the plan's launch shapes (all, or the cost model's top_k), install the fastest."""
+    o = _TuneOpts(reps, warmup, top_k, max_candidates)
+    r = _TuneResult()
+    _check(_lib.moma_ntt_tune(_words(q, limbs), _words(omega, limbs), n, limbs, ctypes.byref(o), ctypes.byref(r)))
+    return {"best": r.best.as_tuple(), "best_us": float(r.best_us), "timed": int(r.timed),
+            "feasible": int(r.feasible)}
+
+
+def ntt_candidates(limbs_compute: int, log2_n: int) -> list:
+    cnt = ctypes.c_uint32(0)
+    _check(_lib.moma_ntt_candidates(limbs_compute, log2_n, None, 0, ctypes.byref(cnt)))
+    arr = (Schedule * max(1, cnt.value))()
+    _check(_lib.moma_ntt_candidates(limbs_compute, log2_n, arr, cnt.value, ctypes.byref(cnt)))
+    return [arr[i].as_tuple() for i in range(cnt.value)]
+
+
+def tune_db_rows() -> list:
+    out = []
+    row = _TuneRow()
+    for i in range(_lib.moma_tune_db_count()):
+        _check(_lib.moma_tune_db_get(i, ctypes.byref(row)))
+        out.append({"limbs": int(row.limbs), "log2_n": int(row.log2_n), "sched": row.sched.as_tuple(),
+                    "us": float(row.us), "reps": int(row.reps)})
+    return out
+
+
+def tune_db_clear():
+    _lib.moma_tune_db_clear()
+
+
+def tune_db_save(path: str):
+    _check(_lib.moma_tune_db_save(path.encode()))
+
+
+def tune_db_load(path: str):
+    _check(_lib.moma_tune_db_load(path.encode()))
+
+
+# ----------------------------------------------------------------- cost model
+
+def costmodel_features(limbs_compute: int, log2_n: int, sched) -> list:
+    out = (ctypes.c_float * 6)()
+    _check(_lib.moma_costmodel_features(limbs_compute, log2_n, ctypes.byref(Schedule(*sched)), out))
+    return list(out)
+
+
+def _f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(_fp)
+
+
+def costmodel_train(features, log_us, epochs: int = 200, batch: int = 256, lr: float = 3e-3, seed: int = 1) -> float:
+    """Train the model on the GPU from features (rows, 6) and log-microsecond targets; returns the final MSE."""
+    f, fp = _f32(features)
+    t, tp = _f32(log_us)
+    mse = ctypes.c_float(0)
+    _check(_lib.moma_costmodel_train(fp, tp, t.shape[0], ctypes.byref(_TrainOpts(epochs, batch, lr, seed)),
+                                     ctypes.byref(mse)))
+    return float(mse.value)
+
+
+def costmodel_predict(features):
+    import numpy as np
+    f, fp = _f32(features)
+    out = np.zeros(f.shape[0], dtype=np.float32)
+    _check(_lib.moma_costmodel_predict(fp, f.shape[0], out.ctypes.data_as(_fp)))
+    return out
+
+
+def costmodel_save(path: str):
+    _check(_lib.moma_costmodel_save(path.encode()))
+
+
+def costmodel_load(path: str):
+    _check(_lib.moma_costmodel_load(path.encode()))
+
+
+def costmodel_clear():
+    _lib.moma_costmodel_clear()
+
+
+def mlp_nparams() -> int:
+    return int(_lib.moma_mlp_nparams())
+
+
+def mlp_forward(params, x, y, stream=None):
+    """y[r] = network(x[r]) on device float32 tensors (params flat, x (rows, 6))."""
+    _check(_lib.moma_mlp_forward(params.data_ptr(), x.data_ptr(), x.shape[0], y.data_ptr(), _stream(stream)))
+    return y
+
+
+def mlp_grad(params, x, t, grad, loss, stream=None):
+    _check(_lib.moma_mlp_grad(params.data_ptr(), x.data_ptr(), t.data_ptr(), x.shape[0], grad.data_ptr(),
+                              loss.data_ptr(), _stream(stream)))
+
+
+def mlp_adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_lib.moma_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, beta1,
+                              beta2, eps, _stream(stream)))
 
 
 def shutdown():

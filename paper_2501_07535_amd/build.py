@@ -27,7 +27,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["blas.hip", "ntt.hip", "capi.cpp", "batch.cpp"]
+SOURCES = ["blas.hip", "ntt.hip", "mlp.hip", "capi.cpp", "batch.cpp", "tune.cpp", "costmodel.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -235,6 +235,13 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   p->logn = 0;
   while ((1ull << p->logn) < n) p->logn++;
   p->sched = default_schedule(fe->f.L, p->logn);
+  NttSchedule tuned;
+  std::vector<NttPass> tuned_passes;
+  std::string keep = g_detail;
+  if (tune_db_best(current_device_name(), fe->f.L, p->logn, &tuned) &&
+      plan_passes(fe->f.L, p->logn, tuned, &tuned_passes) == MOMA_OK)
+    p->sched = tuned;
+  g_detail = keep;
   rc = plan_passes(fe->f.L, p->logn, p->sched, &p->passes);
   if (rc) return rc;
   if (check_planes(*p)) return set_error(MOMA_E_UNSUPPORTED, "no valid pass split for this size");
@@ -260,7 +267,7 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   return MOMA_OK;
 }
 
-static int run_ntt(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s) {
+int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s) {
   const FieldRaw& f = p.fe->f;
   const DirTables& t = inverse ? p.inv : p.fwd;
   std::vector<NttPass> passes;
@@ -310,7 +317,7 @@ static int ntt_entry(bool inverse, const uint32_t* q, const uint32_t* omega, uin
   std::shared_ptr<NttPlan> p;
   int rc = get_plan(q, omega, n, limbs, &p);
   if (rc) return rc;
-  return run_ntt(*p, inverse, d_in, d_out, (hipStream_t)stream);
+  return run_plan(*p, inverse, d_in, d_out, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------ BLAS

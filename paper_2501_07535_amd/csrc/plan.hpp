@@ -55,5 +55,12 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
 uint32_t max_radix_log(int L);
 int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out);
 NttSchedule default_schedule(int L, uint32_t logn);
+int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s);
+// tuner (tune.cpp)
+std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn);
+bool tune_db_best(const std::string& dev, int L, uint32_t logn, NttSchedule* out);
+std::string current_device_name();
+// cost model (costmodel.cpp): predicted log-time per schedule; MOMA_E_UNSUPPORTED without a model
+int costmodel_scores(int L, uint32_t logn, const std::vector<NttSchedule>& cands, std::vector<float>* scores);
 
 }  // namespace moma

@@ -1,0 +1,64 @@
+"""Autotuner, timing database and learned cost model on the GPU."""
+import os
+
+import numpy as np
+import pytest
+
+import moma_inputs as mi
+from gpu_util import from_dev, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_exhaustive_installs_the_fastest(tmp_path):
+    import oracle
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(256, 0)
+    L, n = 8, 1 << 12
+    w = f.root(n)
+    moma.tune_db_clear()
+    say("tune exhaustive 256-bit 2^12")
+    r = moma.ntt_tune(f.q, w, n, L, reps=3, warmup=1)
+    assert r["timed"] == r["feasible"] == len(moma.ntt_candidates(L, 12)) > 5
+    rows = moma.tune_db_rows()
+    assert len(rows) == r["timed"]
+    best = min(rows, key=lambda x: x["us"])
+    assert best["sched"] == r["best"] == moma.ntt_get_schedule(f.q, w, n, L)
+    assert abs(best["us"] - r["best_us"]) < 1e-6 * max(1.0, best["us"])
+    x = mi.residues(f, n, L, 400)
+    assert (from_dev(moma.ntt_fwd(to_dev(x), f.q, w)) == oracle.ntt_radix2(f.q, L, w, x)).all()
+    path = str(tmp_path / "db.csv")
+    moma.tune_db_save(path)
+    moma.tune_db_clear()
+    assert moma.tune_db_rows() == []
+    moma.tune_db_load(path)
+    assert len(moma.tune_db_rows()) == len(rows)
+
+
+def test_costmodel_ranks_and_top_k(tmp_path):
+    import paper_2501_07535_amd as moma
+    moma.tune_db_clear()
+    f = mi.find_prime(128, 0)
+    shapes = [(11, ), (13, ), (14, )]
+    for (logn,) in shapes:
+        say(f"tune 128-bit 2^{logn}")
+        moma.ntt_tune(f.q, f.root(1 << logn), 1 << logn, f.limbs, reps=3, warmup=1)
+    rows = moma.tune_db_rows()
+    feats = np.array([moma.costmodel_features(r["limbs"], r["log2_n"], r["sched"]) for r in rows], np.float32)
+    y = np.log(np.array([r["us"] for r in rows], np.float32))
+    mse = moma.costmodel_train(feats, y, epochs=300, batch=64, lr=3e-3, seed=3)
+    assert mse < np.var(y)                      # better than predicting the mean
+    pred = moma.costmodel_predict(feats)
+    assert np.corrcoef(pred, y)[0, 1] > 0.5
+    path = str(tmp_path / "cm.txt")
+    moma.costmodel_save(path)
+    moma.costmodel_clear()
+    with pytest.raises(moma.MomaError):
+        moma.costmodel_predict(feats)
+    moma.costmodel_load(path)
+    assert np.allclose(moma.costmodel_predict(feats), pred, rtol=1e-5, atol=1e-5)
+    r = moma.ntt_tune(f.q, f.root(1 << 12), 1 << 12, f.limbs, reps=3, warmup=1, top_k=3)
+    assert r["timed"] == 3 and r["feasible"] > 3
+    moma.costmodel_clear()
+    with pytest.raises(moma.MomaError):
+        moma.ntt_tune(f.q, f.root(1 << 12), 1 << 12, f.limbs, top_k=3)
