@@ -143,6 +143,8 @@ typedef struct moma_ntt_schedule {
  * for malformed values.  Affects calls enqueued afterwards. */
 int moma_ntt_set_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
                           const moma_ntt_schedule_t* sched);
+/* The schedule a new plan uses when the timing database has no entry for it. */
+int moma_ntt_default_schedule(uint32_t limbs_compute, uint32_t log2_n, moma_ntt_schedule_t* sched);
 /* Read the schedule the plan currently uses. */
 int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
                           moma_ntt_schedule_t* sched);

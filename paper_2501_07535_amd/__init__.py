@@ -74,6 +74,7 @@ _lib.moma_ntt_set_schedule.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_u
 _lib.moma_ntt_set_schedule.restype = ctypes.c_int
 _lib.moma_ntt_get_schedule.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Schedule)]
 _lib.moma_ntt_get_schedule.restype = ctypes.c_int
+_lib.moma_ntt_default_schedule.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Schedule)]
 
 
 class _Job(ctypes.Structure):
@@ -142,7 +143,7 @@ MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA
 
 EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
             "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_prepare", "moma_ntt_describe",
-            "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_batch_create", "moma_batch_run",
+            "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_ntt_default_schedule", "moma_batch_create", "moma_batch_run",
             "moma_batch_info", "moma_batch_destroy", "moma_ntt_tune", "moma_ntt_candidates", "moma_tune_db_count",
             "moma_tune_db_get", "moma_tune_db_clear", "moma_tune_db_save", "moma_tune_db_load",
             "moma_costmodel_features", "moma_costmodel_train", "moma_costmodel_predict", "moma_costmodel_save",
@@ -285,6 +286,17 @@ def ntt_set_schedule(q: int, omega: int, n: int, limbs: int, sched=None):
     if sched is not None:
         ptr = ctypes.byref(Schedule(*[int(v) for v in sched]))
     _check(_lib.moma_ntt_set_schedule(_words(q, limbs), _words(omega, limbs), n, limbs, ptr))
+
+
+def _default_schedule_for(limbs_compute: int, log2_n: int) -> tuple:
+    s = Schedule()
+    _check(_lib.moma_ntt_default_schedule(limbs_compute, log2_n, ctypes.byref(s)))
+    return s.as_tuple()
+
+
+def ntt_default_schedule(limbs_compute: int, log2_n: int) -> tuple:
+    """The schedule a fresh plan uses without a tuning database entry."""
+    return _default_schedule_for(limbs_compute, log2_n)
 
 
 def ntt_get_schedule(q: int, omega: int, n: int, limbs: int) -> tuple:

@@ -465,6 +465,15 @@ int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, 
   return MOMA_OK;
 }
 
+int moma_ntt_default_schedule(uint32_t limbs_compute, uint32_t log2_n, moma_ntt_schedule_t* sched) {
+  if (!sched) return set_error(MOMA_E_ARG, "sched is NULL");
+  if (limbs_compute < 1 || limbs_compute > (uint32_t)kMaxLimbs || log2_n < 1 || log2_n > MOMA_MAX_LOG_N)
+    return set_error(MOMA_E_ARG, "limbs or log2_n out of range");
+  NttSchedule s = default_schedule((int)limbs_compute, log2_n);
+  *sched = {s.tile_log, s.col_log, s.threads, s.radix_log};
+  return MOMA_OK;
+}
+
 void moma_shutdown(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_plans.clear();
