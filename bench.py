@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-jobs", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -128,6 +130,14 @@ def main():
     launch_ms = ms_step / launches
     achieved = ops / launches / (launch_ms * 1e-3) / 1e12
     peak = PEAK_INT_OPS / 1e12
+
+    if args.calib_copy_mib:
+        src = torch.zeros(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     batch = None
     if not args.no_batch:
