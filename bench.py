@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-jobs", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-tune", action="store_true", help="time the default schedule without autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -85,6 +86,12 @@ def main():
     dz = torch.empty_like(dx)
     moma.ntt_prepare(q, w, n, L)
     stream = torch.cuda.current_stream()
+    default_sched = moma.ntt_get_schedule(q, w, n, L)
+    default_us = _time_fwd(moma, torch, stream, dx, dy, q, w, 3, 20)
+    tuned = None
+    if not args.no_tune:
+        # the library's autotuner picks the launch shape before the timed region
+        tuned = moma.ntt_tune(q, w, n, L, reps=3, warmup=1)
     plan = moma.ntt_describe(q, w, n, L)
     launches = plan["passes"]
 
@@ -168,9 +175,12 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": None,
                      "kernel": f"ntt_pass_kernel<{L}>", "launches_per_step": launches,
                      "avg_launch_us": round(launch_ms * 1e3, 3),
-                     "ops_per_butterfly": alg_ops_per_butterfly(L), "pass_stages": plan["stages"]},
+                     "ops_per_butterfly": alg_ops_per_butterfly(L), "pass_stages": plan["stages"],
+                     "schedule": list(moma.ntt_get_schedule(q, w, n, L))},
         "cpu_baseline": cpu,
         "extras": {"fwd_us": round(ms_step * 1e3, 3), "inv_us": round(ms_inv * 1e3, 3),
+                   "default_schedule": list(default_sched), "default_schedule_fwd_us": round(default_us, 3),
+                   "autotuned": tuned,
                    "ns_per_butterfly_paper_metric": round(2 * ms_step * 1e6 / (n * logn), 6),
                    "hbm_bytes_min_per_step": 2 * n * 4 * L,
                    "roundtrip_exact": roundtrip, "sampled_vs_oracle": sampled_ok,
@@ -178,6 +188,18 @@ def main():
                    "batch": batch},
     }
     print(json.dumps(rec), flush=True)
+
+
+def _time_fwd(moma, torch, stream, dx, dy, q, w, warmup, reps):
+    for _ in range(warmup):
+        moma.ntt_fwd(dx, q, w, out=dy)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        moma.ntt_fwd(dx, q, w, out=dy)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
 
 
 def batch_vs_plain(njobs: int, reps: int):

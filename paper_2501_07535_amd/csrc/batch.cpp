@@ -117,7 +117,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       g.recs.push_back(a);
       size_t off = g.consts.size();
       g.consts.resize(off + cb);
-      ntt_fill_consts(f, job.inverse ? &p->inv_consts : &none, g.consts.data() + off);
+      ntt_fill_consts(f, p->fe->dc, job.inverse ? &p->inv_consts : &none, g.consts.data() + off);
       uint64_t E = 1ull << (ps.k + ps.logc);
       uint64_t cost = E * ps.k;
       auto& v = g.items[(uint32_t)i];

@@ -72,6 +72,20 @@ int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* 
   HBig::divmod(HBig::pow2(2 * Mn + 3), qn, &mu, nullptr);
   if (mu.bitlen() > 32 * f.L) return set_error(MOMA_E_MODULUS, "internal: Barrett constant too wide");
   mu.to_limbs(f.mu, kMaxLimbs);
+  // digit form of the transform's twiddle multiply
+  {
+    DigitConsts& dc = fe->dc;
+    memset(&dc, 0, sizeof(dc));
+    int b = digit_bits(f.L), D = digit_count(f.L);
+    for (int i = 0; i < D; i++) {
+      HBig di = HBig::shr(Q, b * i);
+      uint32_t w[2] = {0, 0};
+      di.to_limbs(w, 2);
+      dc.qd[i] = w[0] & ((1u << b) - 1);
+    }
+    dc.qinvd = f.qinv & ((1u << b) - 1);
+    HBig::mod(HBig::pow2(b * D), Q).to_limbs(dc.adj, kMaxLimbs);
+  }
   fe->Q = Q;
   fe->one_m = one_m;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -178,7 +192,7 @@ static int build_tables(NttPlan& p, const HBig& w, DirTables* t) {
   const FieldRaw& f = p.fe->f;
   const HBig& Q = p.fe->Q;
   int L = f.L;
-  std::vector<uint32_t> lad((size_t)(p.logn + 1) * L);
+  std::vector<uint32_t> lad((size_t)(p.logn + 2) * L);
   HBig cur = w;
   for (uint32_t b = 0; b < p.logn; b++) {
     HBig m = HBig::mulmod(cur, p.fe->one_m, Q);
@@ -186,11 +200,12 @@ static int build_tables(NttPlan& p, const HBig& w, DirTables* t) {
     cur = HBig::mulmod(cur, cur, Q);
   }
   p.fe->one_m.to_limbs(&lad[(size_t)p.logn * L], L);
+  for (int j = 0; j < L; j++) lad[(size_t)(p.logn + 1) * L + j] = p.fe->dc.adj[j];
   int e = upload(&t->ladder, lad);
   if (e) return hip_fail(e, "ladder upload");
-  e = (int)hipMalloc((void**)&t->tw, (size_t)p.n * L * sizeof(uint32_t));
+  e = (int)hipMalloc((void**)&t->tw, (size_t)p.n * digit_stride(L) * sizeof(uint32_t));
   if (e) return set_error(MOMA_E_NOMEM, "twiddle table allocation failed");
-  e = launch_twiddle_gen(f, t->tw, p.n, p.logn, t->ladder, 0);
+  e = launch_twiddle_gen(f, p.fe->dc, t->tw, p.n, p.logn, t->ladder, 0);
   if (e) return hip_fail(e, "twiddle generation launch");
   return MOMA_OK;
 }
@@ -301,7 +316,8 @@ int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hi
     a.logc = ps.logc;
     a.last = (i + 1 == P) ? 1u : 0u;
     a.scale = (inverse && i + 1 == P) ? 1u : 0u;
-    int e = launch_ntt_pass(f, a, inverse ? p.inv_consts : none, sched.threads, ps.tiles, sched.radix_log, s);
+    int e = launch_ntt_pass(f, p.fe->dc, a, inverse ? p.inv_consts : none, sched.threads, ps.tiles, sched.radix_log,
+                            s);
     if (e) return hip_fail(e, "ntt pass launch");
   }
   if (f.Ls > f.L && d_out != d_in) {

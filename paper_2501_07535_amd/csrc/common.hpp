@@ -8,9 +8,16 @@
 namespace moma {
 
 constexpr int kMaxLimbs = 32;
+// Digit form of the transform's twiddle multiply: b-bit digits (b = 29, or 28
+// above 28 limbs), D of them, so that 2D products of two digits plus a carry
+// stay below 2^64 and b*D >= 32L - 2 covers every operand below 4q.
+constexpr int digit_bits(int L) { return L <= 28 ? 29 : 28; }
+constexpr int digit_count(int L) { return (32 * L - 2 + digit_bits(L) - 1) / digit_bits(L); }
+constexpr int digit_stride(int L) { return digit_count(L) + (digit_count(L) & 1); }  // table words per entry
+
 // widest limb counts that get radix-4 / radix-8 register units
-constexpr int kMaxLimbsRadix4 = 12;
-constexpr int kMaxLimbsRadix8 = 8;
+constexpr int kMaxLimbsRadix4 = 10;
+constexpr int kMaxLimbsRadix8 = 5;
 
 // Constants of one modulus, sized for the largest limb count; the launchers copy
 // the first L words of each array into a compile-time sized kernel argument.
@@ -62,25 +69,32 @@ struct NttConsts {
   uint32_t nscale_m[kMaxLimbs];  // n^{-1} * 2^(32L) mod q
 };
 
+// per-modulus constants of the digit-form multiply
+struct DigitConsts {
+  uint32_t qd[40];   // q in b-bit digits
+  uint32_t qinvd;    // -q^{-1} mod 2^b
+  uint32_t adj[kMaxLimbs];  // 2^(b*D) mod q, converts a table entry to digit Montgomery form
+};
+
 // set the thread's error detail and return code
 int set_error(int code, const std::string& detail);
 
 // launchers (return hipError_t as int)
 int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s);
 int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, hipStream_t s);
-int launch_ntt_pass(const FieldRaw& f, const NttPassArgs& a, const NttConsts& c, uint32_t threads, uint64_t tiles,
-                    uint32_t radix_log, hipStream_t s);
+int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& c,
+                    uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s);
 // batched transforms: one launch runs items (pass record, tile) of many plans
 size_t ntt_consts_bytes(int L);
 void ntt_batch_prepare(int L, uint32_t radix_log, size_t lds);
-void ntt_fill_consts(const FieldRaw& f, const NttConsts* nc, void* dst);
+void ntt_fill_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc, void* dst);
 int launch_ntt_batch(int L, uint32_t radix_log, uint32_t threads, size_t lds, uint32_t grid,
                      const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
                      hipStream_t s);
 // largest workgroup the pass kernel for (L, radix_log) was compiled for
 uint32_t ntt_max_threads(int L, uint32_t radix_log);
-int launch_twiddle_gen(const FieldRaw& f, uint32_t* tw, uint64_t n, uint32_t logn, const uint32_t* d_ladder,
-                       hipStream_t s);
+int launch_twiddle_gen(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t n, uint32_t logn,
+                       const uint32_t* d_ladder, hipStream_t s);
 
 
 }  // namespace moma

@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.hpp"
+
 namespace moma {
 
 typedef uint32_t u32;
@@ -53,6 +55,39 @@ __device__ __forceinline__ void mac_vs(u64& acc, u32& hi, u32 x, u32 y) {
       "v_addc_co_u32 %2, %1, %2, 0, %1"
       : "+v"(acc), "=&s"(cy), "+v"(hi)
       : "v"(x), "s"(y));
+}
+
+// acc(64) += x1 * y1 + x2 * y2 with carries into hi; x in VGPRs, y1 VGPR, y2 uniform.
+// One asm statement for two products halves the wait states the compiler
+// inserts after every inline-asm block.
+__device__ __forceinline__ void mac2_vv_vs(u64& acc, u32& hi, u32 x1, u32 y1, u32 x2, u32 y2) {
+  u64 cy;
+  asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+      "v_addc_co_u32 %2, %1, %2, 0, %1\n\t"
+      "v_mad_u64_u32 %0, %1, %5, %6, %0\n\t"
+      "v_addc_co_u32 %2, %1, %2, 0, %1"
+      : "+v"(acc), "=&s"(cy), "+v"(hi)
+      : "v"(x1), "v"(y1), "v"(x2), "s"(y2));
+}
+
+// First products of a column: hi = carry-out (instead of hi += carry-out), so the
+// carry word needs no zeroing move.
+__device__ __forceinline__ void mac2_vv_vs_first(u64& acc, u32& hi, u32 x1, u32 y1, u32 x2, u32 y2) {
+  u64 cy;
+  asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+      "v_addc_co_u32 %2, %1, 0, 0, %1\n\t"
+      "v_mad_u64_u32 %0, %1, %5, %6, %0\n\t"
+      "v_addc_co_u32 %2, %1, %2, 0, %1"
+      : "+v"(acc), "=&s"(cy), "=&v"(hi)
+      : "v"(x1), "v"(y1), "v"(x2), "s"(y2));
+}
+
+__device__ __forceinline__ void mac_vv_first(u64& acc, u32& hi, u32 x, u32 y) {
+  u64 cy;
+  asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+      "v_addc_co_u32 %2, %1, 0, 0, %1"
+      : "+v"(acc), "=&s"(cy), "=&v"(hi)
+      : "v"(x), "v"(y));
 }
 
 // acc(64) += x * y with no carry-out (caller guarantees no overflow).
@@ -152,28 +187,32 @@ template <int L>
 __device__ __forceinline__ void mont_mul_lazy(u32* t, const u32* a, const u32* b, const u32* q, u32 qinv) {
   u32 m[L];
   u64 acc = 0;
-  u32 hi = 0;
+  u32 hi;
 #pragma unroll
   for (int i = 0; i < L; i++) {
+    if (i == 0) {
+      mac_vv_first(acc, hi, a[0], b[0]);
+    } else {
+      mac2_vv_vs_first(acc, hi, a[0], b[i], m[0], q[i]);
 #pragma unroll
-    for (int j = 0; j < i; j++) {
-      mac_vv(acc, hi, a[j], b[i - j]);
-      mac_vs(acc, hi, m[j], q[i - j]);
+      for (int j = 1; j < i; j++) mac2_vv_vs(acc, hi, a[j], b[i - j], m[j], q[i - j]);
+      mac_vv(acc, hi, a[i], b[0]);
     }
-    mac_vv(acc, hi, a[i], b[0]);
     m[i] = (u32)acc * qinv;
     mac_vs(acc, hi, m[i], q[0]);
-    shift_col(acc, hi);
+    acc = (acc >> 32) | ((u64)hi << 32);
   }
 #pragma unroll
   for (int i = L; i < 2 * L; i++) {
+    if (i - L + 1 < L) {
+      mac2_vv_vs_first(acc, hi, a[i - L + 1], b[L - 1], m[i - L + 1], q[L - 1]);
 #pragma unroll
-    for (int j = i - L + 1; j < L; j++) {
-      mac_vv(acc, hi, a[j], b[i - j]);
-      mac_vs(acc, hi, m[j], q[i - j]);
+      for (int j = i - L + 2; j < L; j++) mac2_vv_vs(acc, hi, a[j], b[i - j], m[j], q[i - j]);
+      t[i - L] = (u32)acc;
+      acc = (acc >> 32) | ((u64)hi << 32);
+    } else {
+      t[i - L] = (u32)acc;  // last column: no products left, only the carried word
     }
-    t[i - L] = (u32)acc;
-    shift_col(acc, hi);
   }
   // t < 2q < 2^(32L): the final carry word is zero
 }
@@ -184,6 +223,90 @@ __device__ __forceinline__ void mont_mul(u32* r, const u32* a, const u32* b, con
   u32 t[L];
   mont_mul_lazy<L>(t, a, b, q, qinv);
   reduce_once<L>(r, t, q);
+}
+
+// ----------------------------------------------------------------- digit form
+//
+// The paper's multi-digit numbers may use any digit base z (Eq. (def_mp)).  For
+// the transform's twiddle multiply, residues are re-expressed in base 2^b with
+// b = 29 (28 above 28 limbs) and D digits, chosen so that a column of 2D digit
+// products plus the carried word stays below 2^64.  Every word product is then
+// one v_mad_u64_u32 into a 64-bit accumulator with no carry handling, which the
+// compiler emits from plain C.  Operands stay in 32-bit limbs everywhere else;
+// the multiply converts on the way in and out.
+template <int L>
+struct Digits {
+  static constexpr int b = digit_bits(L);
+  static constexpr int D = digit_count(L);
+  static constexpr u32 mask = (1u << b) - 1;
+};
+
+// d = y in base 2^b (y < 2^(b*D))
+template <int L>
+__device__ __forceinline__ void to_digits(u32* d, const u32* y) {
+  constexpr int b = Digits<L>::b, D = Digits<L>::D;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    constexpr u32 m = Digits<L>::mask;
+    const int pos = b * i, l = pos / 32, s = pos % 32;
+    u32 lo = l < L ? y[l] : 0u, hi = l + 1 < L ? y[l + 1] : 0u;
+    u32 v = s ? __builtin_amdgcn_alignbit(hi, lo, s) : lo;
+    d[i] = v & m;
+  }
+}
+
+// y = the value of digits d, as L 32-bit limbs (the value fits 32L bits)
+template <int L>
+__device__ __forceinline__ void from_digits(u32* y, const u32* d) {
+  constexpr int b = Digits<L>::b, D = Digits<L>::D;
+#pragma unroll
+  for (int j = 0; j < L; j++) {
+    const int pos = 32 * j, i = pos / b, s = pos % b;
+    u32 v = d[i] >> s;
+    if (i + 1 < D && b - s < 32) v |= d[i + 1] << (b - s);
+    if (i + 2 < D && 2 * b - s < 32) v |= d[i + 2] << (2 * b - s);
+    y[j] = v;
+  }
+}
+
+// t = y * w * 2^(-bD) mod q in [0, 2q), w given as digits (Montgomery form for
+// R = 2^(bD)), y < 4q in 32-bit limbs.  Product scanning: column i sums every
+// digit product y_j w_{i-j} and m_j q_{i-j}; m_i = (low b bits) * qinvd mod 2^b
+// clears the low b bits, then the column shifts right by b.  2D^2 products.
+template <int L>
+__device__ __forceinline__ void mont_mul_digits(u32* t, const u32* y, const u32* wd, const u32* qd, u32 qinvd) {
+  constexpr int b = Digits<L>::b, D = Digits<L>::D;
+  constexpr u32 mask = Digits<L>::mask;
+  u32 a[D], m[D], r[D];
+  to_digits<L>(a, y);
+  u64 acc = 0;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+#pragma unroll
+    for (int j = 0; j <= i; j++) acc += (u64)a[j] * wd[i - j];
+#pragma unroll
+    for (int j = 0; j < i; j++) acc += (u64)m[j] * qd[i - j];
+    m[i] = ((u32)acc * qinvd) & mask;
+    acc += (u64)m[i] * qd[0];
+    acc >>= b;
+  }
+#pragma unroll
+  for (int i = D; i < 2 * D - 1; i++) {
+#pragma unroll
+    for (int j = i - D + 1; j < D; j++) acc += (u64)a[j] * wd[i - j] + (u64)m[j] * qd[i - j];
+    r[i - D] = (u32)acc & mask;
+    acc >>= b;
+  }
+  r[D - 1] = (u32)acc;
+  from_digits<L>(t, r);
+}
+
+// Copy uniform words into VGPRs once, opaquely, so carry chains that need the
+// operand in a VGPR do not re-copy it from SGPRs at every use.
+template <int L>
+__device__ __forceinline__ void to_vgprs(u32* dst, const u32* src) {
+#pragma unroll
+  for (int i = 0; i < L; i++) asm volatile("v_mov_b32 %0, %1" : "=v"(dst[i]) : "s"(src[i]));
 }
 
 // Cooley-Tukey butterfly with lazy reduction (Harvey, "Faster arithmetic for
@@ -200,6 +323,33 @@ __device__ __forceinline__ void ct_butterfly_lazy(u32* x, u32* y, const u32* w, 
   add_vv<L>(x, xr, t);
   sub_vv<L>(d, xr, t);
   add_vs<L>(y, d, q2);
+}
+
+// Lazy butterfly with the twiddle in digit form (mont_mul_digits) and 2q in VGPRs.
+template <int L>
+__device__ __forceinline__ void ct_butterfly_digits(u32* x, u32* y, const u32* wd, const u32* qd, u32 qinvd,
+                                                    const u32* q2v) {
+  u32 xr[L], t[L], d[L], s[L];
+  u64 br = sub_vv<L>(s, x, q2v);  // x - 2q; borrow <=> x < 2q
+  select<L>(xr, br, x, s);
+  mont_mul_digits<L>(t, y, wd, qd, qinvd);
+  add_vv<L>(x, xr, t);
+  sub_vv<L>(d, xr, t);
+  add_vv<L>(y, d, q2v);
+}
+
+// The same butterfly with 2q already in VGPRs (q2v); q stays uniform for the
+// multiply's products.
+template <int L>
+__device__ __forceinline__ void ct_butterfly_lazy_v(u32* x, u32* y, const u32* w, const u32* q, const u32* q2v,
+                                                    u32 qinv) {
+  u32 xr[L], t[L], d[L], s[L];
+  u64 br = sub_vv<L>(s, x, q2v);  // x - 2q; borrow <=> x < 2q
+  select<L>(xr, br, x, s);
+  mont_mul_lazy<L>(t, y, w, q, qinv);
+  add_vv<L>(x, xr, t);
+  sub_vv<L>(d, xr, t);
+  add_vv<L>(y, d, q2v);
 }
 
 // Barrett constants for r = a*b mod q, following Listings 1 and 4 generalised to

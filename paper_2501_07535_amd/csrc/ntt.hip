@@ -19,7 +19,8 @@
 //     elements spanning r consecutive stages, so LDS is read and written, and
 //     the workgroup synchronised, once per r stages instead of once per stage.
 //   * Twiddle table: entry m + i' (m = 2^s) holds w_{2m}^{i'} in Montgomery form
-//     (level s stores the first m powers of w_{2m}).  With that order the C
+//     for R = 2^(bD), as D b-bit digits padded to an even word count (level s
+//     stores the first m powers of w_{2m}).  With that order the C
 //     groups of a tile read C consecutive entries, and the first pass reads a
 //     table prefix shared by every tile.
 // Butterflies use lazy reduction: values stay in [0, 4q) between stages and
@@ -34,9 +35,11 @@ namespace moma {
 template <int L>
 struct NttC {
   u32 q[L];
-  u32 q2[L];      // 2q
+  u32 q2[L];                    // 2q
   u32 qinv;
-  u32 nscale[L];  // n^-1 in Montgomery form (inverse transform, last pass)
+  u32 nscale[L];                // n^-1 in Montgomery form (inverse transform, last pass)
+  u32 qd[Digits<L>::D];         // q in b-bit digits (twiddle multiply)
+  u32 qinvd;                    // -q^-1 mod 2^b
 };
 
 __device__ __forceinline__ u32 rev_bits(u32 x, u32 b) { return b ? (__brev(x) >> (32 - b)) : 0u; }
@@ -67,6 +70,18 @@ __device__ __forceinline__ void load_entry(u32* r, const u32* __restrict__ p) {
   }
 }
 
+// one twiddle entry: digit_stride(L) words, 8-byte aligned
+template <int L>
+__device__ __forceinline__ void load_digits(u32* r, const u32* __restrict__ p) {
+  const uint2* v = reinterpret_cast<const uint2*>(p);
+#pragma unroll
+  for (int i = 0; i < digit_stride(L) / 2; i++) {
+    uint2 t = v[i];
+    r[2 * i] = t.x;
+    r[2 * i + 1] = t.y;
+  }
+}
+
 // Tile geometry shared by the load, compute and store phases.
 struct TileGeo {
   u32 k, logc, K, rows, C, E;
@@ -87,6 +102,8 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
   const u32 B = 1u << (k - sg0);        // block size (rows) at stage sg0
   const u32 sub = B >> R;                // row spacing of a unit's elements
   const u32 units = (t.E >> R);
+  u32 q2v[L];
+  to_vgprs<L>(q2v, c.q2);
   for (u32 b = threadIdx.x; b < units; b += blockDim.x) {
     u32 g = b & (t.C - 1), v = b >> t.logc;
     u32 lb = v >> (k - sg0 - R);
@@ -98,14 +115,15 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
       for (int j = 0; j < L; j++) x[e][j] = lds[(j * t.rows + p0 + e * sub) * t.C + g];
 #pragma unroll
     for (int s = 0; s < R; s++) {
-      const int half = 1 << (R - 1 - s);
+      const int kb = R - 1 - s, half = 1 << kb;
 #pragma unroll
-      for (int e = 0; e < (1 << R); e++) {
-        if (e & half) continue;
+      for (int p = 0; p < (1 << (R - 1)); p++) {
+        // p with a zero bit inserted at position kb: the pair (e, e + half) of this stage
+        const int e = ((p >> kb) << (kb + 1)) | (p & (half - 1));
         u32 lbk = (lb << s) + (u32)(e >> (R - s));
-        u32 w[L];
-        load_entry<L>(w, tw + tw_pos(t, sg0 + s, lbk, g) * L);
-        ct_butterfly_lazy<L>(x[e], x[e + half], w, c.q, c.q2, c.qinv);
+        u32 w[digit_stride(L)];
+        load_digits<L>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L));
+        ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
       }
     }
 #pragma unroll
@@ -141,20 +159,44 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
   const u32 tid = threadIdx.x, T = blockDim.x;
   const u64 n = t.n;
 
-  // ---- load (natural order in the first pass, bit-reversed storage after)
-  for (u32 e = tid; e < t.E; e += T) {
-    u32 g = e & (t.C - 1), v = e >> t.logc;
-    u64 src;
-    u32 u;
-    if (t.K == 0) {
-      u = v;
-      src = (u64)u * t.S + t.o0 + g;
-    } else {
-      u = rev_bits(v, t.k);
-      src = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
-    }
+  // ---- load (natural order in the first pass, bit-reversed storage after).
+  // Each lane moves 4 consecutive words per limb: 4 groups of one row when the
+  // tile has C >= 4 groups, else 4 consecutive rows of a one-pass transform.
+  const bool vec_g = t.C >= 4, vec_u = (t.C == 1 && t.S == 1 && t.rows >= 4);
+  if (vec_g || vec_u) {
+    for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
+      u32 e = e4 << 2;
+      u32 g = e & (t.C - 1), v = e >> t.logc;
+      u64 src;
+      u32 u;
+      if (t.K == 0) {
+        u = v;
+        src = (u64)u * t.S + t.o0 + g;
+      } else {
+        u = rev_bits(v, t.k);
+        src = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
+      }
 #pragma unroll
-    for (int j = 0; j < L; j++) lds[(j * t.rows + u) * t.C + g] = a.in[(u64)j * n + src];
+      for (int j = 0; j < L; j++) {
+        uint4 w = *reinterpret_cast<const uint4*>(a.in + (u64)j * n + src);
+        *reinterpret_cast<uint4*>(lds + (j * t.rows + u) * t.C + g) = w;
+      }
+    }
+  } else {
+    for (u32 e = tid; e < t.E; e += T) {
+      u32 g = e & (t.C - 1), v = e >> t.logc;
+      u64 src;
+      u32 u;
+      if (t.K == 0) {
+        u = v;
+        src = (u64)u * t.S + t.o0 + g;
+      } else {
+        u = rev_bits(v, t.k);
+        src = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
+      }
+#pragma unroll
+      for (int j = 0; j < L; j++) lds[(j * t.rows + u) * t.C + g] = a.in[(u64)j * n + src];
+    }
   }
   __syncthreads();
 
@@ -175,26 +217,9 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
     __syncthreads();
   }
 
-  // ---- store
+  // ---- store (canonical residues on the last pass), 4 words per lane per limb
   const u32 logn = a.logn;
-  for (u32 e = tid; e < t.E; e += T) {
-    u32 g, v, u;
-    u64 dst;
-    if (t.K == 0) {
-      // consecutive lanes write consecutive addresses inside one group's run
-      g = e >> t.k;
-      v = e & (t.rows - 1);
-      u = rev_bits(v, t.k);
-      dst = ((u64)rev_bits((u32)(t.o0 + g), logn - t.k) << t.k) + v;
-    } else {
-      g = e & (t.C - 1);
-      v = e >> t.logc;
-      u = rev_bits(v, t.k);
-      dst = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
-    }
-    u32 x[L];
-#pragma unroll
-    for (int j = 0; j < L; j++) x[j] = lds[(j * t.rows + u) * t.C + g];
+  auto finish = [&](u32* x) {
     if (a.last) {
       u32 y[L];
       if (a.scale) {
@@ -204,8 +229,70 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
       }
       reduce_once<L>(x, y, c.q);                         // -> [0, q)
     }
+  };
+  constexpr bool kVecStore = L <= 16;  // 4 elements of L limbs stay in registers
+  if (kVecStore && t.K > 0 && vec_g) {
+    // same addresses as the load: 4 consecutive groups of one row
+    for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
+      u32 e = e4 << 2;
+      u32 g = e & (t.C - 1), v = e >> t.logc;
+      u32 u = rev_bits(v, t.k);
+      u64 dst = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
+      u32 x[4][L];
 #pragma unroll
-    for (int j = 0; j < L; j++) a.out[(u64)j * n + dst] = x[j];
+      for (int j = 0; j < L; j++) {
+        uint4 w = *reinterpret_cast<const uint4*>(lds + (j * t.rows + u) * t.C + g);
+        x[0][j] = w.x;
+        x[1][j] = w.y;
+        x[2][j] = w.z;
+        x[3][j] = w.w;
+      }
+#pragma unroll
+      for (int q4 = 0; q4 < 4; q4++) finish(x[q4]);
+#pragma unroll
+      for (int j = 0; j < L; j++)
+        *reinterpret_cast<uint4*>(a.out + (u64)j * n + dst) = make_uint4(x[0][j], x[1][j], x[2][j], x[3][j]);
+    }
+  } else if (kVecStore && t.K == 0 && t.rows >= 4) {
+    // 4 consecutive output addresses inside one group's run of 2^k
+    for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
+      u32 e = e4 << 2;
+      u32 g = e >> t.k, v = e & (t.rows - 1);
+      u64 dst = ((u64)rev_bits((u32)(t.o0 + g), logn - t.k) << t.k) + v;
+      u32 x[4][L];
+#pragma unroll
+      for (int q4 = 0; q4 < 4; q4++) {
+        u32 u = rev_bits(v + q4, t.k);
+#pragma unroll
+        for (int j = 0; j < L; j++) x[q4][j] = lds[(j * t.rows + u) * t.C + g];
+        finish(x[q4]);
+      }
+#pragma unroll
+      for (int j = 0; j < L; j++)
+        *reinterpret_cast<uint4*>(a.out + (u64)j * n + dst) = make_uint4(x[0][j], x[1][j], x[2][j], x[3][j]);
+    }
+  } else {
+    for (u32 e = tid; e < t.E; e += T) {
+      u32 g, v, u;
+      u64 dst;
+      if (t.K == 0) {
+        g = e >> t.k;
+        v = e & (t.rows - 1);
+        u = rev_bits(v, t.k);
+        dst = ((u64)rev_bits((u32)(t.o0 + g), logn - t.k) << t.k) + v;
+      } else {
+        g = e & (t.C - 1);
+        v = e >> t.logc;
+        u = rev_bits(v, t.k);
+        dst = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
+      }
+      u32 x[L];
+#pragma unroll
+      for (int j = 0; j < L; j++) x[j] = lds[(j * t.rows + u) * t.C + g];
+      finish(x);
+#pragma unroll
+      for (int j = 0; j < L; j++) a.out[(u64)j * n + dst] = x[j];
+    }
   }
 }
 
@@ -247,7 +334,7 @@ __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_ker
 template <int L>
 __global__ __launch_bounds__(256) void twiddle_kernel(u32* __restrict__ tw, u64 n, u32 logn,
                                                       const u32* __restrict__ ladder, NttC<L> c,
-                                                      const u32* __restrict__ one_m) {
+                                                      const u32* __restrict__ one_m, const u32* __restrict__ adj) {
   u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   u32 acc[L];
@@ -268,13 +355,22 @@ __global__ __launch_bounds__(256) void twiddle_kernel(u32* __restrict__ tw, u64 
       }
     }
   }
+  // acc = w^x * 2^(32L); times 2^(bD) * 2^(-32L) gives the digit-form Montgomery value
+  u32 ad[L], wm[L], d[digit_stride(L)];
 #pragma unroll
-  for (int j = 0; j < L; j++) tw[e * L + j] = acc[j];
+  for (int j = 0; j < L; j++) ad[j] = adj[j];
+  mont_mul<L>(wm, acc, ad, c.q, c.qinv);
+  to_digits<L>(d, wm);
+  if (digit_stride(L) > Digits<L>::D) d[digit_stride(L) - 1] = 0;
+#pragma unroll
+  for (int j = 0; j < digit_stride(L); j++) tw[e * digit_stride(L) + j] = d[j];
 }
 
 template <int L>
-static NttC<L> make_consts(const FieldRaw& f, const NttConsts* nc) {
+static NttC<L> make_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc) {
   NttC<L> c;
+  for (int j = 0; j < Digits<L>::D; j++) c.qd[j] = dc.qd[j];
+  c.qinvd = dc.qinvd;
   u64 carry = 0;
   for (int j = 0; j < L; j++) {
     c.q[j] = f.q[j];
@@ -301,9 +397,9 @@ static int launch_pass_LR(const NttC<L>& c, const NttPassArgs& a, uint32_t threa
 }
 
 template <int L>
-static int launch_pass_L(const FieldRaw& f, const NttPassArgs& a, const NttConsts& nc, uint32_t threads,
-                         uint64_t tiles, uint32_t radix_log, hipStream_t s) {
-  NttC<L> c = make_consts<L>(f, &nc);
+static int launch_pass_L(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& nc,
+                         uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s) {
+  NttC<L> c = make_consts<L>(f, dc, &nc);
   // register blocking is limited by the VGPR budget: 2^r elements of L limbs
   if (radix_log == 1) return launch_pass_LR<L, 1>(c, a, threads, tiles, s);
   if constexpr (L <= kMaxLimbsRadix4) {
@@ -320,11 +416,11 @@ uint32_t ntt_max_threads(int L, uint32_t radix_log) {
   return live <= 16 ? 1024u : (live <= 32 ? 512u : 256u);
 }
 
-int launch_ntt_pass(const FieldRaw& f, const NttPassArgs& a, const NttConsts& c, uint32_t threads, uint64_t tiles,
-                    uint32_t radix_log, hipStream_t s) {
+int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& c,
+                    uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s) {
   switch (f.L) {
 #define CASE(LL) \
-  case LL: return launch_pass_L<LL>(f, a, c, threads, tiles, radix_log, s);
+  case LL: return launch_pass_L<LL>(f, dc, a, c, threads, tiles, radix_log, s);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }
@@ -404,11 +500,11 @@ size_t ntt_consts_bytes(int L) {
   return 0;
 }
 
-void ntt_fill_consts(const FieldRaw& f, const NttConsts* nc, void* dst) {
+void ntt_fill_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc, void* dst) {
   switch (f.L) {
 #define CASE(LL)                                  \
   case LL: {                                      \
-    NttC<LL> c = make_consts<LL>(f, nc);          \
+    NttC<LL> c = make_consts<LL>(f, dc, nc);      \
     memcpy(dst, &c, sizeof(c));                   \
     return;                                       \
   }
@@ -418,21 +514,23 @@ void ntt_fill_consts(const FieldRaw& f, const NttConsts* nc, void* dst) {
 }
 
 template <int L>
-static int launch_tw_L(const FieldRaw& f, uint32_t* tw, uint64_t n, uint32_t logn, const uint32_t* d_ladder,
-                       hipStream_t s) {
-  NttC<L> c = make_consts<L>(f, nullptr);
-  // the ladder buffer carries one_m after the logn ladder entries
+static int launch_tw_L(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t n, uint32_t logn,
+                       const uint32_t* d_ladder, hipStream_t s) {
+  NttC<L> c = make_consts<L>(f, dc, nullptr);
+  // the ladder buffer carries one_m and then adj after the logn ladder entries
   const u32* one_m = d_ladder + (size_t)logn * L;
+  const u32* adj = one_m + L;
   u64 blocks = (n + 255) / 256;
-  hipLaunchKernelGGL((twiddle_kernel<L>), dim3((unsigned)blocks), dim3(256), 0, s, tw, n, logn, d_ladder, c, one_m);
+  hipLaunchKernelGGL((twiddle_kernel<L>), dim3((unsigned)blocks), dim3(256), 0, s, tw, n, logn, d_ladder, c, one_m,
+                     adj);
   return (int)hipGetLastError();
 }
 
-int launch_twiddle_gen(const FieldRaw& f, uint32_t* tw, uint64_t n, uint32_t logn, const uint32_t* d_ladder,
-                       hipStream_t s) {
+int launch_twiddle_gen(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t n, uint32_t logn,
+                       const uint32_t* d_ladder, hipStream_t s) {
   switch (f.L) {
 #define CASE(LL) \
-  case LL: return launch_tw_L<LL>(f, tw, n, logn, d_ladder, s);
+  case LL: return launch_tw_L<LL>(f, dc, tw, n, logn, d_ladder, s);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }

@@ -15,6 +15,7 @@ namespace moma {
 
 struct FieldEntry {
   FieldRaw f;
+  DigitConsts dc;
   HBig Q, one_m;
   // last axpy scalar, cached with its Montgomery form
   std::vector<uint32_t> alpha_key;
@@ -22,8 +23,8 @@ struct FieldEntry {
 };
 
 struct DirTables {
-  uint32_t* tw = nullptr;      // n entries x L words, Montgomery form
-  uint32_t* ladder = nullptr;  // (logn + 1) x L words: w^(2^b) in Montgomery form, then 1
+  uint32_t* tw = nullptr;      // n entries x digit_stride(L) words, digit Montgomery form
+  uint32_t* ladder = nullptr;  // (logn + 2) x L words: w^(2^b) in Montgomery form, then 1, then 2^(bD) mod q
 };
 
 struct NttPlan {
