@@ -60,9 +60,48 @@ def parse():
     ap.add_argument("--batch-jobs", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="time the default schedule without autotuning")
+    ap.add_argument("--schedule", default=None,
+                    help="tile_log,col_log,threads,radix_log: use this launch shape instead of autotuning")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the headline line, print one JSON line per size of the transform sweep "
+                         "(2^16..2^24 at 256 bits, 2^20 at 128/384/1024 bits)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def sweep(args):
+    """One line per sweep size: autotuned single-call time, steady state over k, and
+    the oracle's sampled outputs."""
+    import torch
+
+    import oracle
+    import paper_2501_07535_amd as moma
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    for lam, logn in [(256, l) for l in range(16, 25)] + [(128, 20), (384, 20), (1024, 20)]:
+        f = mi.find_prime(lam, 0)
+        L, n, q = f.limbs, 1 << logn, f.q
+        w = f.root(n)
+        x = mi.residues(f, n, L, 2, logn)
+        dx = torch.from_numpy(mi.to_planar(x).view(np.int32)).to(dev)
+        dy = torch.empty_like(dx)
+        moma.ntt_prepare(q, w, n, L)
+        tuned = moma.ntt_tune(q, w, n, L, reps=3, warmup=1)
+        steps = max(3, min(50, int(2e5 / max(tuned["best_us"], 1.0))))
+        us = _time_fwd(moma, torch, stream, dx, dy, q, w, 2, steps)
+        ks = np.array([0, 1, n - 1], dtype=np.int64)
+        got = mi.from_planar(dy[:, torch.from_numpy(ks).to(dev)].cpu().numpy().view(np.uint32))
+        ok = bool((got == oracle.ntt_direct(q, L, w, x, ks)).all())
+        st = steady_state(moma, torch, stream, dx, q, w, n, L, logn, ks=(1, 4, 16) if logn <= 22 else (1, 2))
+        B = n // 2 * logn
+        print(json.dumps({"lambda": lam, "limbs": L, "log2_n": logn, "fwd_us": round(us, 2),
+                          "gbutterfly_s": round(B / us / 1e3, 3), "steady_state": st,
+                          "schedule": list(moma.ntt_get_schedule(q, w, n, L)),
+                          "int_ops_frac": round(alg_ops_per_butterfly(L) * B / (us * 1e-6) / PEAK_INT_OPS, 4),
+                          "sampled_vs_oracle": ok}), flush=True)
+        del dx, dy
+        moma.shutdown()
 
 
 def main():
@@ -71,6 +110,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the transform path is "
               "single-GPU in this build", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        sweep(args)
+        return
     import torch
 
     import paper_2501_07535_amd as moma
@@ -89,7 +131,9 @@ def main():
     default_sched = moma.ntt_get_schedule(q, w, n, L)
     default_us = _time_fwd(moma, torch, stream, dx, dy, q, w, 3, 20)
     tuned = None
-    if not args.no_tune:
+    if args.schedule:
+        moma.ntt_set_schedule(q, w, n, L, tuple(int(v) for v in args.schedule.split(",")))
+    elif not args.no_tune:
         # the library's autotuner picks the launch shape before the timed region
         tuned = moma.ntt_tune(q, w, n, L, reps=3, warmup=1)
     plan = moma.ntt_describe(q, w, n, L)
@@ -146,6 +190,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    steady = None
+    if not args.no_batch:
+        steady = steady_state(moma, torch, stream, dx, q, w, n, L, logn)
+
     batch = None
     if not args.no_batch:
         batch = batch_vs_plain(args.batch_jobs, args.batch_reps)
@@ -172,7 +220,8 @@ def main():
                    "lambda": lam, "limbs": L, "q_bits": q.bit_length(), "log2_n": logn,
                    "layout": "limb-planar", "twiddles": "precomputed table"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "Tops/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4),
+                     "traffic": measured_traffic(lam, logn, moma.ntt_get_schedule(q, w, n, L)),
                      "kernel": f"ntt_pass_kernel<{L}>", "launches_per_step": launches,
                      "avg_launch_us": round(launch_ms * 1e3, 3),
                      "ops_per_butterfly": alg_ops_per_butterfly(L), "pass_stages": plan["stages"],
@@ -184,10 +233,27 @@ def main():
                    "ns_per_butterfly_paper_metric": round(2 * ms_step * 1e6 / (n * logn), 6),
                    "hbm_bytes_min_per_step": 2 * n * 4 * L,
                    "roundtrip_exact": roundtrip, "sampled_vs_oracle": sampled_ok,
+                   "steady_state": steady,
                    "batched_vs_plain_speedup": batch["speedup"] if batch else None,
                    "batch": batch},
     }
     print(json.dumps(rec), flush=True)
+
+
+def measured_traffic(lam, logn, schedule):
+    """HBM bytes per pass-kernel launch from the committed rocprofv3 counters, if
+    they were taken on the current kernel sources with this launch shape."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"ntt_traffic_L{(lam + 31) // 32}_{lam}bit_n2e{logn}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["kernel_sources_sha256"] or list(rec["schedule"]) != list(schedule):
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def _time_fwd(moma, torch, stream, dx, dy, q, w, warmup, reps):
@@ -200,6 +266,34 @@ def _time_fwd(moma, torch, stream, dx, dy, q, w, warmup, reps):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def steady_state(moma, torch, stream, dx, q, w, n, L, logn, ks=(1, 2, 4, 8, 16)):
+    """The paper's steady-state protocol (Section 5.1): t_single = t_all / k for a
+    batch of k transforms of this size, minimised over k; here each batch is one
+    graph launch of the batched executor over k independent buffers."""
+    outs = [torch.empty_like(dx) for _ in range(max(ks))]
+    ins = [dx.clone() for _ in range(max(ks))]
+    res = {}
+    for k in ks:
+        b = moma.Batch([(ins[i], outs[i], q, w, False) for i in range(k)])
+        b.run()
+        torch.cuda.synchronize()
+        reps = max(3, 32 // k)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[k] = e0.elapsed_time(e1) * 1e3 / reps / k
+        b.close()
+    same = all(torch.equal(outs[i], outs[0]) for i in range(max(ks)))
+    kbest = min(res, key=res.get)
+    B = n // 2 * logn
+    return {"us_per_transform_by_k": {str(k): round(v, 3) for k, v in res.items()}, "best_k": kbest,
+            "us_per_transform": round(res[kbest], 3), "gbutterfly_s": round(B / (res[kbest] * 1e-6) / 1e9, 3),
+            "outputs_identical": same}
 
 
 def batch_vs_plain(njobs: int, reps: int):
