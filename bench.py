@@ -175,6 +175,8 @@ def main():
     except Exception as e:  # the oracle is optional for the measurement itself
         print(f"oracle check skipped: {e}", file=sys.stderr)
 
+    cyc = cyclic_product(moma, torch, stream, dx, dy, dz, q, w, n, args.warmup, args.steps)
+
     B = n // 2 * logn
     gbfly = B / (ms_step * 1e-3) / 1e9
     ops = alg_ops_per_butterfly(L) * B
@@ -234,6 +236,7 @@ def main():
                    "hbm_bytes_min_per_step": 2 * n * 4 * L,
                    "roundtrip_exact": roundtrip, "sampled_vs_oracle": sampled_ok,
                    "steady_state": steady,
+                   "cyclic_product": cyc,
                    "batched_vs_plain_speedup": batch["speedup"] if batch else None,
                    "batch": batch},
     }
@@ -254,6 +257,44 @@ def measured_traffic(lam, logn, schedule):
     if h.hexdigest() != rec["kernel_sources_sha256"] or list(rec["schedule"]) != list(schedule):
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def cyclic_product(moma, torch, stream, da, db, dc, q, w, n, warmup, reps):
+    """Cyclic product a * b mod (x^n - 1) of two resident vectors: the fused call
+    (pointwise product inside the inverse transform's first pass) against the
+    same steps as four separate calls (fwd, fwd, vmul, inv).  Checked outside
+    the timed region: a product with x^s is a rotation by s."""
+    ta, tb = torch.empty_like(da), torch.empty_like(da)
+
+    def fused():
+        moma.ntt_cyclic_mul(da, db, q, w, out=dc)
+
+    def unfused():
+        moma.ntt_fwd(da, q, w, out=ta)
+        moma.ntt_fwd(db, q, w, out=tb)
+        moma.vmul(ta, tb, q, out=ta)
+        moma.ntt_inv(ta, q, w, out=dc)
+
+    res = {}
+    for name, fn in (("fused_us", fused), ("unfused_us", unfused)):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = round(e0.elapsed_time(e1) * 1e3 / reps, 3)
+    s = 12345 % n
+    shift = torch.zeros_like(da)
+    shift[0, s] = 1
+    moma.ntt_cyclic_mul(da, shift, q, w, out=dc)
+    torch.cuda.synchronize()
+    res["shift_is_rotation"] = bool(torch.equal(dc, torch.roll(da, s, dims=1)))
+    res["fused_speedup"] = round(res["unfused_us"] / res["fused_us"], 3)
+    del ta, tb, shift
+    return res
 
 
 def _time_fwd(moma, torch, stream, dx, dy, q, w, warmup, reps):

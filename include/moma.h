@@ -35,7 +35,10 @@
  *   d_out == d_y); partial overlap is undefined.  Work is enqueued on
  *   `stream` (a hipStream_t passed as void*; NULL is the default stream) and
  *   returns without synchronising.  Plan creation may allocate device memory
- *   and synchronise once.  The plan cache is thread safe.
+ *   and synchronise once.  The plan cache is thread safe.  A plan's scratch
+ *   (used by in-place multi-pass transforms and by the cyclic product) is one
+ *   buffer per plan: such calls for the same plan on different streams must
+ *   not run at the same time.
  *
  * Errors
  *   Functions return MOMA_OK (0) or a negative code; moma_strerror() names
@@ -103,6 +106,21 @@ int moma_ntt_fwd(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t 
                  uint32_t* d_out, void* stream);
 int moma_ntt_inv(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const uint32_t* d_in,
                  uint32_t* d_out, void* stream);
+
+/*
+ * Cyclic product of two polynomials of n coefficients (the use of the NTT in
+ * Section 2.3, via the convolution theorem):
+ *   d_out[k] = sum over i + j == k (mod n) of d_a[i] * d_b[j]  mod q,
+ * that is a * b mod (x^n - 1).  Same arguments and preconditions as
+ * moma_ntt_fwd; omega is a primitive n-th root (any one gives the same
+ * result).  Runs fwd(a), fwd(b) and the inverse transform, whose first pass
+ * multiplies the two spectra pointwise as it loads them: no separate
+ * pointwise kernel and no extra pass over memory.  d_out may equal d_a or
+ * d_b.  The first call for a plan allocates 2 * n * L words of spectra
+ * scratch (L = compute limbs), kept with the plan.
+ */
+int moma_ntt_cyclic_mul(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const uint32_t* d_a,
+                        const uint32_t* d_b, uint32_t* d_out, void* stream);
 
 /*
  * Build (or look up) the plan for (q, omega, n, limbs) without running a
@@ -242,22 +260,27 @@ int moma_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, 
 /*
  * Batched transforms (the paper batches kernels to fill the GPU, Section 5.1):
  * many NTTs of different sizes, limb counts and moduli run as one hipGraph
- * launch.  A job is one transform of the kind moma_ntt_fwd / moma_ntt_inv run,
- * with the same argument meanings and preconditions; its plan is built (and
- * shared with identical jobs) by moma_batch_create.  The batch keeps the job
- * buffers' addresses: they must stay allocated, and are read and written by
- * every moma_batch_run.  Each job's output equals what the plain call with the
- * same arguments produces, bit for bit.  Jobs must not overlap one another's
- * output buffers.
+ * launch.  A job is one call of the kind moma_ntt_fwd, moma_ntt_inv or
+ * moma_ntt_cyclic_mul runs, with the same argument meanings and
+ * preconditions; its plan is built (and shared with identical jobs) by
+ * moma_batch_create, and a cyclic product gets 2 * n * L words of spectra
+ * scratch of its own, owned by the batch.  The batch keeps the job buffers'
+ * addresses: they must stay allocated, and are read and written by every
+ * moma_batch_run.  Each job's output equals what the plain call with the same
+ * arguments produces, bit for bit.  Jobs must not overlap one another's
+ * output buffers, and no job may read another job's output.
  */
+enum moma_job_kind { MOMA_JOB_FORWARD = 0, MOMA_JOB_INVERSE = 1, MOMA_JOB_CYCLIC_MUL = 2 };
+
 typedef struct moma_ntt_job {
   const uint32_t* q;      /* host, limbs words */
   const uint32_t* omega;  /* host, limbs words: forward primitive n-th root */
   uint64_t n;
   uint32_t limbs;
-  uint32_t inverse;       /* 0 forward, 1 inverse */
-  const uint32_t* d_in;   /* device, limb-planar */
-  uint32_t* d_out;        /* device, limb-planar; may equal d_in */
+  uint32_t kind;          /* enum moma_job_kind */
+  const uint32_t* d_in;   /* device, limb-planar (cyclic product: a) */
+  uint32_t* d_out;        /* device, limb-planar; may equal d_in (or d_in2) */
+  const uint32_t* d_in2;  /* device, limb-planar: b of a cyclic product; ignored otherwise */
 } moma_ntt_job_t;
 
 typedef struct moma_batch* moma_batch_t;

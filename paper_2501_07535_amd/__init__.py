@@ -54,6 +54,8 @@ _lib.moma_axpy.restype = ctypes.c_int
 for _name in ("moma_ntt_fwd", "moma_ntt_inv"):
     getattr(_lib, _name).argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
     getattr(_lib, _name).restype = ctypes.c_int
+_lib.moma_ntt_cyclic_mul.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp, _vp]
+_lib.moma_ntt_cyclic_mul.restype = ctypes.c_int
 _lib.moma_ntt_prepare.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32]
 _lib.moma_ntt_prepare.restype = ctypes.c_int
 _lib.moma_ntt_describe.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _u32p, _u32p, ctypes.c_uint32,
@@ -79,7 +81,10 @@ _lib.moma_ntt_default_schedule.argtypes = [ctypes.c_uint32, ctypes.c_uint32, cty
 
 class _Job(ctypes.Structure):
     _fields_ = [("q", _u32p), ("omega", _u32p), ("n", ctypes.c_uint64), ("limbs", ctypes.c_uint32),
-                ("inverse", ctypes.c_uint32), ("d_in", _vp), ("d_out", _vp)]
+                ("kind", ctypes.c_uint32), ("d_in", _vp), ("d_out", _vp), ("d_in2", _vp)]
+
+
+JOB_FORWARD, JOB_INVERSE, JOB_CYCLIC_MUL = 0, 1, 2
 
 
 _lib.moma_batch_create.argtypes = [ctypes.POINTER(_Job), ctypes.c_uint32, ctypes.POINTER(_vp)]
@@ -142,7 +147,7 @@ _lib.moma_shutdown.restype = None
 MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
-            "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_prepare", "moma_ntt_describe",
+            "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_cyclic_mul", "moma_ntt_prepare", "moma_ntt_describe",
             "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_ntt_default_schedule", "moma_batch_create", "moma_batch_run",
             "moma_batch_info", "moma_batch_destroy", "moma_ntt_tune", "moma_ntt_candidates", "moma_tune_db_count",
             "moma_tune_db_get", "moma_tune_db_clear", "moma_tune_db_save", "moma_tune_db_load",
@@ -265,6 +270,19 @@ def ntt_inv(y, q: int, omega: int, out=None, stream=None):
     return out
 
 
+def ntt_cyclic_mul(a, b, q: int, omega: int, out=None, stream=None):
+    """Cyclic product out = a * b mod (x^n - 1, q): inv(fwd(a) . fwd(b)), the pointwise
+    product fused into the inverse transform's first pass."""
+    _dev(a, "a"); _dev(b, "b")
+    if a.shape != b.shape:
+        raise ValueError("a and b must have the same shape")
+    limbs, n = a.shape
+    out = _out(a, out)
+    _check(_lib.moma_ntt_cyclic_mul(_words(q, limbs), _words(omega, limbs), n, limbs, a.data_ptr(), b.data_ptr(),
+                                    out.data_ptr(), _stream(stream)))
+    return out
+
+
 def ntt_prepare(q: int, omega: int, n: int, limbs: int):
     """Build the plan (twiddle tables) for (q, omega, n, limbs) ahead of timed calls."""
     _check(_lib.moma_ntt_prepare(_words(q, limbs), _words(omega, limbs), n, limbs))
@@ -308,22 +326,33 @@ def ntt_get_schedule(q: int, omega: int, n: int, limbs: int) -> tuple:
 class Batch:
     """Many transforms run as one graph launch.
 
-    jobs: iterable of (x, out, q, omega, inverse) with x / out limb-planar device
-    tensors of shape (limbs, n) (out may be x).  The batch keeps references to
-    the tensors; run() recomputes every job from its current input.
+    jobs: iterable of (x, out, q, omega, kind) with x / out limb-planar device
+    tensors of shape (limbs, n) (out may be x).  kind is JOB_FORWARD (or False),
+    JOB_INVERSE (or True) or JOB_CYCLIC_MUL; for a cyclic product x is the pair
+    (a, b).  The batch keeps references to the tensors; run() recomputes every
+    job from its current inputs.
     """
 
     def __init__(self, jobs):
         self._keep = []
         recs = []
-        for x, out, q, omega, inverse in jobs:
+        for x, out, q, omega, kind in jobs:
+            kind = int(kind)
+            if kind not in (JOB_FORWARD, JOB_INVERSE, JOB_CYCLIC_MUL):
+                raise ValueError(f"unknown job kind {kind}")
+            if kind == JOB_CYCLIC_MUL:
+                x, x2 = x
+                _dev(x2, "b")
+                if x2.shape != x.shape:
+                    raise ValueError("a and b must have the same shape")
+                self._keep.append(x2)
             _dev(x, "x")
             _dev(out, "out")
             limbs, n = x.shape
             qw, ww = _words(q, limbs), _words(omega, limbs)
             self._keep += [x, out, qw, ww]
-            recs.append(_Job(ctypes.cast(qw, _u32p), ctypes.cast(ww, _u32p), n, limbs, 1 if inverse else 0,
-                             x.data_ptr(), out.data_ptr()))
+            recs.append(_Job(ctypes.cast(qw, _u32p), ctypes.cast(ww, _u32p), n, limbs, kind, x.data_ptr(),
+                             out.data_ptr(), x2.data_ptr() if kind == JOB_CYCLIC_MUL else None))
         arr = (_Job * len(recs))(*recs)
         h = _vp()
         _check(_lib.moma_batch_create(arr, len(recs), ctypes.byref(h)))

@@ -27,7 +27,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["blas.hip", "ntt.hip", "mlp.hip", "capi.cpp", "batch.cpp", "tune.cpp", "costmodel.cpp"]
+SOURCES = ["ntt_inst_d.hip", "ntt_inst_c.hip", "ntt_inst_b.hip", "ntt_inst_a.hip", "ntt.hip", "blas.hip", "mlp.hip",
+           "capi.cpp", "batch.cpp", "tune.cpp", "costmodel.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -3,8 +3,11 @@
 // reports steady-state time per transform, Section 5.1).
 //
 // Every job is split into the passes of its own plan.  Pass p of every job
-// forms phase p; within a phase, jobs are grouped by compute limb count (the
-// kernels are compiled per limb count) and each group becomes one launch of
+// forms phase p (a cyclic product runs its two forward transforms in phases
+// 0 .. P-1 and its inverse in phases P .. 2P-1); within a phase, jobs are
+// grouped by compute limb count (the
+// kernels are compiled per limb count) and by their plans' register radix and
+// workgroup size, and each group becomes one launch of
 // ntt_batch_kernel over a flat list of (pass record, tile) items, sorted by
 // decreasing work and dealt round-robin to a fixed grid.  Phases follow one
 // another in stream order, which is the only dependency between a job's
@@ -16,6 +19,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <tuple>
 #include <vector>
 
 #include "../../include/moma.h"
@@ -26,6 +30,7 @@ namespace moma {
 
 struct BatchLaunch {
   int L;
+  bool mul;
   uint32_t radix_log, threads, grid, nitems;
   size_t lds;
   const NttPassArgs* d_passes;
@@ -74,64 +79,96 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     std::map<uint32_t, std::vector<std::pair<uint64_t, uint2>>> items;  // phase -> (cost, item)
     std::map<uint32_t, size_t> lds;                                     // phase -> max tile bytes
   };
-  std::map<int, Group> groups;
-  for (uint32_t j = 0; j < njobs; j++) {
-    const moma_ntt_job_t& job = jobs[j];
-    if (!job.d_in || !job.d_out) return set_error(MOMA_E_ARG, "job " + std::to_string(j) + ": NULL buffer");
-    if (job.inverse > 1) return set_error(MOMA_E_ARG, "job " + std::to_string(j) + ": inverse must be 0 or 1");
-    std::shared_ptr<NttPlan> p;
-    int rc = get_plan(job.q, job.omega, job.n, job.limbs, &p);
-    if (rc) return set_error(rc, "job " + std::to_string(j) + ": " + g_detail);
-    b.plans.push_back(p);
-    const FieldRaw& f = p->fe->f;
-    std::vector<NttPass> passes;
-    {
-      std::lock_guard<std::mutex> lk(p->mu);
-      passes = p->passes;
-    }
-    uint32_t* first_out = job.d_out;
-    if (passes.size() > 1 && job.d_in == job.d_out) {
-      void* s = nullptr;
-      if (hipMalloc(&s, (size_t)p->n * f.L * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, "job scratch");
-      b.dev_allocs.push_back(s);
-      first_out = (uint32_t*)s;
-    }
-    Group& g = groups[f.L];
+  // key: (compute limbs, register radix, threads) of the job's plan schedule,
+  // and whether the pass multiplies two inputs (first inverse pass of a
+  // cyclic product: a kernel variant of its own)
+  typedef std::tuple<int, uint32_t, uint32_t, bool> GKey;
+  std::map<GKey, Group> groups;
+  NttConsts none;
+  memset(&none, 0, sizeof(none));
+  // one transform of a job: its passes go to phases phase0, phase0 + 1, ...
+  auto add = [&](NttPlan& p, const NttSchedule& sched, const std::vector<NttPass>& passes, const DirTables& t,
+                 const NttConsts& nc, bool scale, const uint32_t* in, const uint32_t* in2, uint32_t* first_out,
+                 uint32_t* out, uint32_t phase0) {
+    const FieldRaw& f = p.fe->f;
     size_t cb = ntt_consts_bytes(f.L);
-    NttConsts none;
-    memset(&none, 0, sizeof(none));
     for (size_t i = 0; i < passes.size(); i++) {
       const NttPass& ps = passes[i];
-      NttPassArgs a;
-      a.in = (i == 0) ? job.d_in : (i == 1 ? first_out : job.d_out);
-      a.out = (i == 0) ? first_out : job.d_out;
-      a.tw = job.inverse ? p->inv.tw : p->fwd.tw;
-      a.n = p->n;
-      a.logn = p->logn;
+      Group& g = groups[GKey(f.L, sched.radix_log, sched.threads, i == 0 && in2 != nullptr)];
+      NttPassArgs a{};
+      a.in = (i == 0) ? in : (i == 1 ? first_out : out);
+      a.in2 = (i == 0) ? in2 : nullptr;
+      a.out = (i == 0) ? first_out : out;
+      a.tw = t.tw;
+      a.n = p.n;
+      a.logn = p.logn;
       a.K = ps.K;
       a.k = ps.k;
       a.logc = ps.logc;
       a.last = (i + 1 == passes.size()) ? 1u : 0u;
-      a.scale = (job.inverse && i + 1 == passes.size()) ? 1u : 0u;
+      a.scale = (scale && i + 1 == passes.size()) ? 1u : 0u;
       uint32_t rec = (uint32_t)g.recs.size();
       g.recs.push_back(a);
       size_t off = g.consts.size();
       g.consts.resize(off + cb);
-      ntt_fill_consts(f, p->fe->dc, job.inverse ? &p->inv_consts : &none, g.consts.data() + off);
+      ntt_fill_consts(f, p.fe->dc, &nc, g.consts.data() + off);
       uint64_t E = 1ull << (ps.k + ps.logc);
       uint64_t cost = E * ps.k;
-      auto& v = g.items[(uint32_t)i];
-      for (uint64_t t = 0; t < ps.tiles; t++) v.push_back({cost, make_uint2(rec, (uint32_t)t)});
+      uint32_t ph = phase0 + (uint32_t)i;
+      auto& v = g.items[ph];
+      for (uint64_t tl = 0; tl < ps.tiles; tl++) v.push_back({cost, make_uint2(rec, (uint32_t)tl)});
       size_t bytes = (size_t)E * f.L * sizeof(uint32_t);
-      g.lds[(uint32_t)i] = std::max(g.lds[(uint32_t)i], bytes);
+      g.lds[ph] = std::max(g.lds[ph], bytes);
     }
+  };
+  for (uint32_t j = 0; j < njobs; j++) {
+    const moma_ntt_job_t& job = jobs[j];
+    const std::string tag = "job " + std::to_string(j) + ": ";
+    if (!job.d_in || !job.d_out) return set_error(MOMA_E_ARG, tag + "NULL buffer");
+    if (job.kind > MOMA_JOB_CYCLIC_MUL) return set_error(MOMA_E_ARG, tag + "unknown job kind");
+    if (job.kind == MOMA_JOB_CYCLIC_MUL && !job.d_in2) return set_error(MOMA_E_ARG, tag + "NULL second input");
+    std::shared_ptr<NttPlan> p;
+    int rc = get_plan(job.q, job.omega, job.n, job.limbs, &p);
+    if (rc) return set_error(rc, tag + g_detail);
+    b.plans.push_back(p);
+    const FieldRaw& f = p->fe->f;
+    std::vector<NttPass> passes;
+    NttSchedule sched;
+    {
+      std::lock_guard<std::mutex> lk(p->mu);
+      passes = p->passes;
+      sched = p->sched;
+    }
+    const size_t plane_words = (size_t)p->n * f.L;
+    if (job.kind == MOMA_JOB_CYCLIC_MUL) {
+      void* s = nullptr;
+      if (hipMalloc(&s, 2 * plane_words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, tag + "spectra");
+      b.dev_allocs.push_back(s);
+      uint32_t* sa = (uint32_t*)s;
+      uint32_t* sb = sa + plane_words;
+      add(*p, sched, passes, p->fwd, none, false, job.d_in, nullptr, sa, sa, 0);
+      add(*p, sched, passes, p->fwd, none, false, job.d_in2, nullptr, sb, sb, 0);
+      add(*p, sched, passes, p->inv, p->mul_consts, true, sa, sb, job.d_out, job.d_out, (uint32_t)passes.size());
+      if (f.Ls > f.L) b.fills.push_back({job.d_out, p->n, f.L, f.Ls});
+      continue;
+    }
+    const bool inverse = job.kind == MOMA_JOB_INVERSE;
+    uint32_t* first_out = job.d_out;
+    if (passes.size() > 1 && job.d_in == job.d_out) {
+      void* s = nullptr;
+      if (hipMalloc(&s, plane_words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, tag + "scratch");
+      b.dev_allocs.push_back(s);
+      first_out = (uint32_t*)s;
+    }
+    add(*p, sched, passes, inverse ? p->inv : p->fwd, inverse ? p->inv_consts : none, inverse, job.d_in, nullptr,
+        first_out, job.d_out, 0);
     if (f.Ls > f.L && job.d_out != job.d_in) b.fills.push_back({job.d_out, p->n, f.L, f.Ls});
   }
   // upload tables and build the launch list, phase by phase
   uint32_t max_phase = 0;
   for (auto& kv : groups)
     for (auto& it : kv.second.items) max_phase = std::max(max_phase, it.first + 1);
-  std::map<int, std::pair<void*, void*>> dev_recs;
+  std::map<GKey, std::pair<void*, void*>> dev_recs;
   for (auto& kv : groups) {
     void *dp = nullptr, *dc = nullptr;
     int rc = dev_upload(b, kv.second.recs.data(), kv.second.recs.size() * sizeof(NttPassArgs), &dp);
@@ -142,7 +179,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
   }
   for (uint32_t ph = 0; ph < max_phase; ph++) {
     for (auto& kv : groups) {
-      int L = kv.first;
+      int L = std::get<0>(kv.first);
       auto it = kv.second.items.find(ph);
       if (it == kv.second.items.end() || it->second.empty()) continue;
       auto& v = it->second;
@@ -154,13 +191,14 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       if (rc) return rc;
       BatchLaunch bl;
       bl.L = L;
-      bl.radix_log = std::min(2u, max_radix_log(L));
-      bl.threads = std::min(256u, ntt_max_threads(L, bl.radix_log));
+      bl.mul = std::get<3>(kv.first);
+      bl.radix_log = std::get<1>(kv.first);
+      bl.threads = std::get<2>(kv.first);
       bl.lds = kv.second.lds[ph];
       bl.nitems = (uint32_t)items.size();
       bl.grid = std::min<uint32_t>(bl.nitems, 4096);
-      bl.d_passes = (const NttPassArgs*)dev_recs[L].first;
-      bl.d_consts = dev_recs[L].second;
+      bl.d_passes = (const NttPassArgs*)dev_recs[kv.first].first;
+      bl.d_consts = dev_recs[kv.first].second;
       bl.d_items = (const uint2*)di;
       b.launches.push_back(bl);
       b.items += bl.nitems;
@@ -172,8 +210,8 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
   if (hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal)) return hip_fail(1, "begin capture");
   int err = 0;
   for (const BatchLaunch& bl : b.launches) {
-    err = launch_ntt_batch(bl.L, bl.radix_log, bl.threads, bl.lds, bl.grid, bl.d_passes, bl.d_consts, bl.d_items,
-                           bl.nitems, b.cap);
+    err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.threads, bl.lds, bl.grid, bl.d_passes, bl.d_consts,
+                           bl.d_items, bl.nitems, b.cap);
     if (err) break;
   }
   if (!err)

@@ -265,6 +265,12 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   HBig nscale = HBig::mulmod(ninv, fe->one_m, Q);
   memset(&p->inv_consts, 0, sizeof(p->inv_consts));
   nscale.to_limbs(p->inv_consts.nscale_m, kMaxLimbs);
+  // the fused pointwise product of a cyclic product leaves a factor 2^(-bD)
+  // (digit-form Montgomery): its last pass scales by n^-1 2^(bD) instead
+  const int Lc = fe->f.L;
+  HBig rd = HBig::powmod(HBig(2), HBig((uint64_t)digit_bits(Lc) * (uint64_t)digit_count(Lc)), Q);
+  memset(&p->mul_consts, 0, sizeof(p->mul_consts));
+  HBig::mulmod(nscale, rd, Q).to_limbs(p->mul_consts.nscale_m, kMaxLimbs);
   rc = build_tables(*p, W, &p->fwd);
   if (rc) return rc;
   rc = build_tables(*p, Winv, &p->inv);
@@ -282,9 +288,38 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   return MOMA_OK;
 }
 
+// Enqueue the passes of one transform over the compute limbs.  d_in2, when
+// set, is multiplied into d_in element by element as the first pass loads
+// (a Montgomery product, so c must carry the matching scale).  first_out is
+// where the first pass writes when there are several (the later ones work in
+// place on d_out).
+static int enqueue_passes(NttPlan& p, const std::vector<NttPass>& passes, const NttSchedule& sched,
+                          const DirTables& t, const NttConsts& c, bool scale, const uint32_t* d_in,
+                          const uint32_t* d_in2, uint32_t* first_out, uint32_t* d_out, hipStream_t s) {
+  const FieldRaw& f = p.fe->f;
+  size_t P = passes.size();
+  for (size_t i = 0; i < P; i++) {
+    const NttPass& ps = passes[i];
+    NttPassArgs a{};
+    a.in = (i == 0) ? d_in : (i == 1 ? first_out : d_out);
+    a.in2 = (i == 0) ? d_in2 : nullptr;
+    a.out = (i == 0) ? first_out : d_out;
+    a.tw = t.tw;
+    a.n = p.n;
+    a.logn = p.logn;
+    a.K = ps.K;
+    a.k = ps.k;
+    a.logc = ps.logc;
+    a.last = (i + 1 == P) ? 1u : 0u;
+    a.scale = (scale && i + 1 == P) ? 1u : 0u;
+    int e = launch_ntt_pass(f, p.fe->dc, a, c, sched.threads, ps.tiles, sched.radix_log, s);
+    if (e) return hip_fail(e, "ntt pass launch");
+  }
+  return MOMA_OK;
+}
+
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s) {
   const FieldRaw& f = p.fe->f;
-  const DirTables& t = inverse ? p.inv : p.fwd;
   std::vector<NttPass> passes;
   NttSchedule sched;
   uint32_t* first_out = d_out;
@@ -300,27 +335,46 @@ int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hi
       first_out = p.scratch;
     }
   }
-  size_t P = passes.size();
   NttConsts none;
   memset(&none, 0, sizeof(none));
-  for (size_t i = 0; i < P; i++) {
-    const NttPass& ps = passes[i];
-    NttPassArgs a;
-    a.in = (i == 0) ? d_in : (i == 1 ? first_out : d_out);
-    a.out = (i == 0) ? first_out : d_out;
-    a.tw = t.tw;
-    a.n = p.n;
-    a.logn = p.logn;
-    a.K = ps.K;
-    a.k = ps.k;
-    a.logc = ps.logc;
-    a.last = (i + 1 == P) ? 1u : 0u;
-    a.scale = (inverse && i + 1 == P) ? 1u : 0u;
-    int e = launch_ntt_pass(f, p.fe->dc, a, inverse ? p.inv_consts : none, sched.threads, ps.tiles, sched.radix_log,
-                            s);
-    if (e) return hip_fail(e, "ntt pass launch");
-  }
+  int rc = enqueue_passes(p, passes, sched, inverse ? p.inv : p.fwd, inverse ? p.inv_consts : none, inverse, d_in,
+                          nullptr, first_out, d_out, s);
+  if (rc) return rc;
   if (f.Ls > f.L && d_out != d_in) {
+    int e = launch_zero_planes(d_out, p.n, f.L, f.Ls, s);
+    if (e) return hip_fail(e, "zero planes launch");
+  }
+  return MOMA_OK;
+}
+
+// Cyclic product a * b mod (x^n - 1): both forward transforms go to the
+// plan's spectra buffer, and the inverse transform's first pass multiplies
+// them pointwise while loading (digit-form Montgomery, a factor 2^(-bD)); its
+// last pass scales by n^-1 2^(bD), which cancels that factor.
+int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s) {
+  const FieldRaw& f = p.fe->f;
+  std::vector<NttPass> passes;
+  NttSchedule sched;
+  uint32_t* spec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(p.mu);
+    passes = p.passes;
+    sched = p.sched;
+    if (!p.spectra) {
+      if (hipMalloc((void**)&p.spectra, 2 * (size_t)p.n * f.L * sizeof(uint32_t)))
+        return set_error(MOMA_E_NOMEM, "spectra allocation failed");
+    }
+    spec = p.spectra;
+  }
+  uint32_t* sa = spec;
+  uint32_t* sb = spec + (size_t)p.n * f.L;
+  NttConsts none;
+  memset(&none, 0, sizeof(none));
+  int rc = enqueue_passes(p, passes, sched, p.fwd, none, false, d_a, nullptr, sa, sa, s);
+  if (!rc) rc = enqueue_passes(p, passes, sched, p.fwd, none, false, d_b, nullptr, sb, sb, s);
+  if (!rc) rc = enqueue_passes(p, passes, sched, p.inv, p.mul_consts, true, sa, sb, d_out, d_out, s);
+  if (rc) return rc;
+  if (f.Ls > f.L) {
     int e = launch_zero_planes(d_out, p.n, f.L, f.Ls, s);
     if (e) return hip_fail(e, "zero planes launch");
   }
@@ -431,6 +485,15 @@ int moma_ntt_fwd(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t 
 int moma_ntt_inv(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const uint32_t* d_in,
                  uint32_t* d_out, void* stream) {
   return ntt_entry(true, q, omega, n, limbs, d_in, d_out, stream);
+}
+
+int moma_ntt_cyclic_mul(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const uint32_t* d_a,
+                        const uint32_t* d_b, uint32_t* d_out, void* stream) {
+  if (!d_a || !d_b || !d_out) return set_error(MOMA_E_ARG, "device pointer is NULL");
+  std::shared_ptr<NttPlan> p;
+  int rc = get_plan(q, omega, n, limbs, &p);
+  if (rc) return rc;
+  return run_cyclic_mul(*p, d_a, d_b, d_out, (hipStream_t)stream);
 }
 
 int moma_ntt_prepare(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs) {

@@ -50,6 +50,7 @@ struct NttPass {
 
 struct NttPassArgs {
   const uint32_t* in;
+  const uint32_t* in2;  // first pass only: multiply in by in2 pointwise while loading (Montgomery, NULL = off)
   uint32_t* out;
   const uint32_t* tw;  // twiddle table, element-major, L words per entry
   uint64_t n;
@@ -66,7 +67,7 @@ struct NttSchedule {
 };
 
 struct NttConsts {
-  uint32_t nscale_m[kMaxLimbs];  // n^{-1} * 2^(32L) mod q
+  uint32_t nscale_m[kMaxLimbs];  // n^{-1} * 2^(32L) mod q (times 2^(bD) after a fused pointwise product)
 };
 
 // per-modulus constants of the digit-form multiply
@@ -88,7 +89,7 @@ int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs&
 size_t ntt_consts_bytes(int L);
 void ntt_batch_prepare(int L, uint32_t radix_log, size_t lds);
 void ntt_fill_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc, void* dst);
-int launch_ntt_batch(int L, uint32_t radix_log, uint32_t threads, size_t lds, uint32_t grid,
+int launch_ntt_batch(int L, uint32_t radix_log, bool mul, uint32_t threads, size_t lds, uint32_t grid,
                      const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
                      hipStream_t s);
 // largest workgroup the pass kernel for (L, radix_log) was compiled for

@@ -1,0 +1,562 @@
+// ntt_impl.hpp - number theoretic transform kernels (paper Eq. (ntt),
+// Section 5.3) and their per-limb-count launchers, as templates.  ntt.hip
+// dispatches on the limb count at run time; the instantiations for each limb
+// count live in the ntt_inst_*.hip units, so they compile in parallel.
+//
+// Algorithm: radix-2 Cooley-Tukey butterflies (U + V*W, U - V*W), natural-order
+// input.  Stage s (s = 0 .. log2 n - 1) has 2^s blocks; block i pairs elements
+// t = n / 2^(s+1) apart and multiplies by W = w_{2m}^{rev_s(i)} with m = 2^s,
+// w_{2m} = w^(n/2m).  After the last stage element p holds y[rev(p)].
+//
+// Data movement (MI355X-first): stages are grouped into passes of k stages that
+// run in LDS, so each pass reads and writes every element once in HBM.
+//   * Between passes the logical element p is stored at address rev_n(p).  The
+//     first pass reads natural order and writes bit-reversed; later passes read
+//     and write the same addresses (in place); after the last pass address j
+//     holds y[j]: the output comes out in natural order with no extra pass.
+//   * A pass over stages [K, K+k) works on groups of 2^k elements that share a
+//     level-K block and an offset.  A tile is C groups whose addresses are
+//     consecutive (C >= 16 words per limb plane per row), so global loads and
+//     stores are coalesced in every pass.
+//   * Inside a tile, each thread runs radix-2^r units in registers: 2^r
+//     elements spanning r consecutive stages, so LDS is read and written, and
+//     the workgroup synchronised, once per r stages instead of once per stage.
+//   * Twiddle table: entry m + i' (m = 2^s) holds w_{2m}^{i'} in Montgomery form
+//     for R = 2^(bD), as D b-bit digits padded to an even word count (level s
+//     stores the first m powers of w_{2m}).  With that order the C
+//     groups of a tile read C consecutive entries, and the first pass reads a
+//     table prefix shared by every tile.
+// Butterflies use lazy reduction: values stay in [0, 4q) between stages and
+// between passes, and the last pass stores canonical residues in [0, q).
+#pragma once
+#include <string.h>
+
+#include "common.hpp"
+#include "limb.hpp"
+
+namespace moma {
+
+template <int L>
+struct NttC {
+  u32 q[L];
+  u32 q2[L];                    // 2q
+  u32 qinv;
+  u32 nscale[L];                // n^-1 in Montgomery form (inverse transform, last pass)
+  u32 qd[Digits<L>::D];         // q in b-bit digits (twiddle multiply)
+  u32 qinvd;                    // -q^-1 mod 2^b
+};
+
+__device__ __forceinline__ u32 rev_bits(u32 x, u32 b) { return b ? (__brev(x) >> (32 - b)) : 0u; }
+
+template <int L>
+__device__ __forceinline__ void load_entry(u32* r, const u32* __restrict__ p) {
+  if constexpr (L % 4 == 0) {
+    const uint4* v = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < L / 4; i++) {
+      uint4 t = v[i];
+      r[4 * i] = t.x;
+      r[4 * i + 1] = t.y;
+      r[4 * i + 2] = t.z;
+      r[4 * i + 3] = t.w;
+    }
+  } else if constexpr (L % 2 == 0) {
+    const uint2* v = reinterpret_cast<const uint2*>(p);
+#pragma unroll
+    for (int i = 0; i < L / 2; i++) {
+      uint2 t = v[i];
+      r[2 * i] = t.x;
+      r[2 * i + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < L; i++) r[i] = p[i];
+  }
+}
+
+// one twiddle entry: digit_stride(L) words, 8-byte aligned
+template <int L>
+__device__ __forceinline__ void load_digits(u32* r, const u32* __restrict__ p) {
+  const uint2* v = reinterpret_cast<const uint2*>(p);
+#pragma unroll
+  for (int i = 0; i < digit_stride(L) / 2; i++) {
+    uint2 t = v[i];
+    r[2 * i] = t.x;
+    r[2 * i + 1] = t.y;
+  }
+}
+
+// Tile geometry shared by the load, compute and store phases.
+struct TileGeo {
+  u32 k, logc, K, rows, C, E;
+  u64 n, S, o0, ro, b0;
+};
+
+// twiddle table position for local stage sg, local block lb of group g
+__device__ __forceinline__ u64 tw_pos(const TileGeo& t, u32 sg, u32 lb, u32 g) {
+  return (t.K == 0) ? ((1ull << sg) + rev_bits(lb, sg))
+                    : ((1ull << (t.K + sg)) + ((u64)rev_bits(lb, sg) << t.K) + t.b0 + g);
+}
+
+// One round of R stages [sg0, sg0+R) on every radix-2^R unit of the tile.
+template <int L, int R>
+__device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, const u32* __restrict__ tw,
+                                          const NttC<L>& c) {
+  const u32 k = t.k;
+  const u32 B = 1u << (k - sg0);        // block size (rows) at stage sg0
+  const u32 sub = B >> R;                // row spacing of a unit's elements
+  const u32 units = (t.E >> R);
+  u32 q2v[L];
+  to_vgprs<L>(q2v, c.q2);
+  for (u32 b = threadIdx.x; b < units; b += blockDim.x) {
+    u32 g = b & (t.C - 1), v = b >> t.logc;
+    u32 lb = v >> (k - sg0 - R);
+    u32 p0 = lb * B + (v & (sub - 1));
+    u32 x[1 << R][L];
+#pragma unroll
+    for (int e = 0; e < (1 << R); e++)
+#pragma unroll
+      for (int j = 0; j < L; j++) x[e][j] = lds[(j * t.rows + p0 + e * sub) * t.C + g];
+#pragma unroll
+    for (int s = 0; s < R; s++) {
+      const int kb = R - 1 - s, half = 1 << kb;
+#pragma unroll
+      for (int p = 0; p < (1 << (R - 1)); p++) {
+        // p with a zero bit inserted at position kb: the pair (e, e + half) of this stage
+        const int e = ((p >> kb) << (kb + 1)) | (p & (half - 1));
+        u32 lbk = (lb << s) + (u32)(e >> (R - s));
+        u32 w[digit_stride(L)];
+        load_digits<L>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L));
+        ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < (1 << R); e++)
+#pragma unroll
+      for (int j = 0; j < L; j++) lds[(j * t.rows + p0 + e * sub) * t.C + g] = x[e][j];
+  }
+}
+
+
+// One tile of one pass: stages [K, K+k) on C = 2^logc groups of 2^k elements.
+// LDS holds the tile limb-planar: word (j * 2^k + u) * C + g is limb j of row u
+// of group g, so lanes with consecutive g touch consecutive banks.
+// Fused pointwise product of a cyclic product's first inverse pass:
+// r = x * y * 2^(-bD) mod q in [0, 2q) for x, y < q (the digit-form multiply
+// with y converted to digits; the last pass's scale constant carries 2^(bD)).
+template <int L>
+__device__ __forceinline__ void pointwise_digits(u32* r, const u32* x, const u32* y, const NttC<L>& c) {
+  u32 yd[Digits<L>::D];
+  to_digits<L>(yd, y);
+  mont_mul_digits<L>(r, x, yd, c.qd, c.qinvd);
+}
+
+// MUL: the pass also multiplies its input by a.in2 element by element as it
+// loads (first pass of the inverse transform inside a cyclic product).
+template <int L, int R, bool MUL>
+__device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const NttC<L>& c, u64 tile) {
+  TileGeo t;
+  t.k = a.k;
+  t.logc = a.logc;
+  t.K = a.K;
+  t.C = 1u << t.logc;
+  t.rows = 1u << t.k;
+  t.E = t.rows << t.logc;
+  t.n = a.n;
+  t.S = t.n >> (t.K + t.k);
+  t.o0 = t.ro = t.b0 = 0;
+  if (t.K == 0) {
+    t.o0 = tile << t.logc;
+  } else {
+    u64 per = (1ull << t.K) >> t.logc;
+    t.ro = tile / per;
+    t.b0 = (tile % per) << t.logc;
+  }
+  const u32 tid = threadIdx.x, T = blockDim.x;
+  const u64 n = t.n;
+
+  // ---- load (natural order in the first pass, bit-reversed storage after).
+  // Each lane moves 4 consecutive words per limb: 4 groups of one row when the
+  // tile has C >= 4 groups, else 4 consecutive rows of a one-pass transform.
+  const bool vec_g = t.C >= 4, vec_u = (t.C == 1 && t.S == 1 && t.rows >= 4);
+  if (vec_g || vec_u) {
+    for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
+      u32 e = e4 << 2;
+      u32 g = e & (t.C - 1), v = e >> t.logc;
+      u64 src;
+      u32 u;
+      if (t.K == 0) {
+        u = v;
+        src = (u64)u * t.S + t.o0 + g;
+      } else {
+        u = rev_bits(v, t.k);
+        src = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
+      }
+      if constexpr (MUL && L <= 8) {
+        // 4 elements of each input in registers, multiplied pointwise
+        u32 x[4][L], y[4][L];
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+          uint4 w = *reinterpret_cast<const uint4*>(a.in + (u64)j * n + src);
+          uint4 z = *reinterpret_cast<const uint4*>(a.in2 + (u64)j * n + src);
+          x[0][j] = w.x; x[1][j] = w.y; x[2][j] = w.z; x[3][j] = w.w;
+          y[0][j] = z.x; y[1][j] = z.y; y[2][j] = z.z; y[3][j] = z.w;
+        }
+        u32 r[4][L];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; q4++) pointwise_digits<L>(r[q4], x[q4], y[q4], c);
+#pragma unroll
+        for (int j = 0; j < L; j++)
+          *reinterpret_cast<uint4*>(lds + (j * t.rows + u) * t.C + g) = make_uint4(r[0][j], r[1][j], r[2][j], r[3][j]);
+      } else if constexpr (MUL) {
+        // wider limbs, fewer live registers: stage the first input in LDS as
+        // the plain load does, then multiply one element at a time; each lane
+        // rereads only the 4 consecutive LDS words (4 groups of one row, or 4
+        // rows when C == 1) that it wrote itself
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+          uint4 w = *reinterpret_cast<const uint4*>(a.in + (u64)j * n + src);
+          *reinterpret_cast<uint4*>(lds + (j * t.rows + u) * t.C + g) = w;
+        }
+#pragma unroll 1
+        for (u32 q4 = 0; q4 < 4; q4++) {
+          u32 x[L], y[L], r[L];
+#pragma unroll
+          for (int j = 0; j < L; j++) {
+            x[j] = lds[(j * t.rows + u) * t.C + g + q4];
+            y[j] = a.in2[(u64)j * n + src + q4];
+          }
+          pointwise_digits<L>(r, x, y, c);
+#pragma unroll
+          for (int j = 0; j < L; j++) lds[(j * t.rows + u) * t.C + g + q4] = r[j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+          uint4 w = *reinterpret_cast<const uint4*>(a.in + (u64)j * n + src);
+          *reinterpret_cast<uint4*>(lds + (j * t.rows + u) * t.C + g) = w;
+        }
+      }
+    }
+  } else {
+    for (u32 e = tid; e < t.E; e += T) {
+      u32 g = e & (t.C - 1), v = e >> t.logc;
+      u64 src;
+      u32 u;
+      if (t.K == 0) {
+        u = v;
+        src = (u64)u * t.S + t.o0 + g;
+      } else {
+        u = rev_bits(v, t.k);
+        src = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
+      }
+      if constexpr (MUL) {
+        u32 x[L], y[L], r[L];
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+          x[j] = a.in[(u64)j * n + src];
+          y[j] = a.in2[(u64)j * n + src];
+        }
+        pointwise_digits<L>(r, x, y, c);
+#pragma unroll
+        for (int j = 0; j < L; j++) lds[(j * t.rows + u) * t.C + g] = r[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < L; j++) lds[(j * t.rows + u) * t.C + g] = a.in[(u64)j * n + src];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- stages, R at a time in registers
+  u32 sg = 0;
+  while (sg < t.k) {
+    u32 rem = t.k - sg;
+    if (R >= 3 && rem >= 3) {
+      ntt_round<L, (R >= 3 ? 3 : 1)>(lds, t, sg, a.tw, c);
+      sg += (R >= 3 ? 3 : 1);
+    } else if (R >= 2 && rem >= 2) {
+      ntt_round<L, (R >= 2 ? 2 : 1)>(lds, t, sg, a.tw, c);
+      sg += (R >= 2 ? 2 : 1);
+    } else {
+      ntt_round<L, 1>(lds, t, sg, a.tw, c);
+      sg += 1;
+    }
+    __syncthreads();
+  }
+
+  // ---- store (canonical residues on the last pass), 4 words per lane per limb
+  const u32 logn = a.logn;
+  auto finish = [&](u32* x) {
+    if (a.last) {
+      u32 y[L];
+      if (a.scale) {
+        mont_mul_lazy<L>(y, x, c.nscale, c.q, c.qinv);  // x < 4q, nscale < q: y in [0, 2q)
+      } else {
+        reduce_once<L>(y, x, c.q2);                      // [0, 4q) -> [0, 2q)
+      }
+      reduce_once<L>(x, y, c.q);                         // -> [0, q)
+    }
+  };
+  constexpr bool kVecStore = L <= 16;  // 4 elements of L limbs stay in registers
+  if (kVecStore && t.K > 0 && vec_g) {
+    // same addresses as the load: 4 consecutive groups of one row
+    for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
+      u32 e = e4 << 2;
+      u32 g = e & (t.C - 1), v = e >> t.logc;
+      u32 u = rev_bits(v, t.k);
+      u64 dst = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
+      u32 x[4][L];
+#pragma unroll
+      for (int j = 0; j < L; j++) {
+        uint4 w = *reinterpret_cast<const uint4*>(lds + (j * t.rows + u) * t.C + g);
+        x[0][j] = w.x;
+        x[1][j] = w.y;
+        x[2][j] = w.z;
+        x[3][j] = w.w;
+      }
+#pragma unroll
+      for (int q4 = 0; q4 < 4; q4++) finish(x[q4]);
+#pragma unroll
+      for (int j = 0; j < L; j++)
+        *reinterpret_cast<uint4*>(a.out + (u64)j * n + dst) = make_uint4(x[0][j], x[1][j], x[2][j], x[3][j]);
+    }
+  } else if (kVecStore && t.K == 0 && t.rows >= 4) {
+    // 4 consecutive output addresses inside one group's run of 2^k
+    for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
+      u32 e = e4 << 2;
+      u32 g = e >> t.k, v = e & (t.rows - 1);
+      u64 dst = ((u64)rev_bits((u32)(t.o0 + g), logn - t.k) << t.k) + v;
+      u32 x[4][L];
+#pragma unroll
+      for (int q4 = 0; q4 < 4; q4++) {
+        u32 u = rev_bits(v + q4, t.k);
+#pragma unroll
+        for (int j = 0; j < L; j++) x[q4][j] = lds[(j * t.rows + u) * t.C + g];
+        finish(x[q4]);
+      }
+#pragma unroll
+      for (int j = 0; j < L; j++)
+        *reinterpret_cast<uint4*>(a.out + (u64)j * n + dst) = make_uint4(x[0][j], x[1][j], x[2][j], x[3][j]);
+    }
+  } else {
+    for (u32 e = tid; e < t.E; e += T) {
+      u32 g, v, u;
+      u64 dst;
+      if (t.K == 0) {
+        g = e >> t.k;
+        v = e & (t.rows - 1);
+        u = rev_bits(v, t.k);
+        dst = ((u64)rev_bits((u32)(t.o0 + g), logn - t.k) << t.k) + v;
+      } else {
+        g = e & (t.C - 1);
+        v = e >> t.logc;
+        u = rev_bits(v, t.k);
+        dst = (t.ro << (t.K + t.k)) + ((u64)v << t.K) + t.b0 + g;
+      }
+      u32 x[L];
+#pragma unroll
+      for (int j = 0; j < L; j++) x[j] = lds[(j * t.rows + u) * t.C + g];
+      finish(x);
+#pragma unroll
+      for (int j = 0; j < L; j++) a.out[(u64)j * n + dst] = x[j];
+    }
+  }
+}
+
+// Workgroup size cap per instantiation: a radix-2^R unit keeps 2^R elements of
+// L limbs live, so wider units get fewer threads and more VGPRs per lane.
+template <int L, int R>
+struct PassTraits {
+  static constexpr int live = L << R;
+  static constexpr int max_threads = live <= 16 ? 1024 : (live <= 32 ? 512 : 256);
+};
+
+// One pass of one transform: workgroup b runs tile b.
+template <int L, int R, bool MUL>
+__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a, NttC<L> c) {
+  extern __shared__ u32 lds[];
+  pass_tile<L, R, MUL>(lds, a, c, blockIdx.x);
+}
+
+// One phase of a batch: items[i] = (pass record, tile); every pass record names
+// its own transform (buffers, size, stages, twiddles) and its modulus constants.
+// Items are sorted by decreasing cost and dealt round-robin to a fixed grid.
+template <int L, int R, bool MUL>
+__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_kernel(
+    const NttPassArgs* __restrict__ passes, const NttC<L>* __restrict__ consts, const uint2* __restrict__ items,
+    u32 nitems) {
+  extern __shared__ u32 lds[];
+  for (u32 i = blockIdx.x; i < nitems; i += gridDim.x) {
+    uint2 it = items[i];
+    const NttPassArgs a = passes[it.x];
+    const NttC<L> c = consts[it.x];
+    pass_tile<L, R, MUL>(lds, a, c, it.y);
+    __syncthreads();
+  }
+}
+
+// Twiddle table: entry e = 2^s + i' holds w^(i' * 2^(logn-s-1)) * 2^(32L) mod q.
+// ladder[b] = w^(2^b) * 2^(32L) mod q; the product of the ladder entries for the
+// set bits of the exponent stays in Montgomery form.
+template <int L>
+__global__ __launch_bounds__(256) void twiddle_kernel(u32* __restrict__ tw, u64 n, u32 logn,
+                                                      const u32* __restrict__ ladder, NttC<L> c,
+                                                      const u32* __restrict__ one_m, const u32* __restrict__ adj) {
+  u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  u32 acc[L];
+#pragma unroll
+  for (int j = 0; j < L; j++) acc[j] = one_m[j];
+  if (e > 0) {
+    u32 s = 63 - __builtin_clzll(e);
+    u64 ip = e - (1ull << s);
+    u64 x = ip << (logn - s - 1);
+    for (u32 bit = 0; bit < logn; bit++) {
+      if ((x >> bit) & 1) {
+        u32 w[L], t[L];
+#pragma unroll
+        for (int j = 0; j < L; j++) w[j] = ladder[bit * L + j];
+        mont_mul<L>(t, acc, w, c.q, c.qinv);
+#pragma unroll
+        for (int j = 0; j < L; j++) acc[j] = t[j];
+      }
+    }
+  }
+  // acc = w^x * 2^(32L); times 2^(bD) * 2^(-32L) gives the digit-form Montgomery value
+  u32 ad[L], wm[L], d[digit_stride(L)];
+#pragma unroll
+  for (int j = 0; j < L; j++) ad[j] = adj[j];
+  mont_mul<L>(wm, acc, ad, c.q, c.qinv);
+  to_digits<L>(d, wm);
+  if (digit_stride(L) > Digits<L>::D) d[digit_stride(L) - 1] = 0;
+#pragma unroll
+  for (int j = 0; j < digit_stride(L); j++) tw[e * digit_stride(L) + j] = d[j];
+}
+
+template <int L>
+inline NttC<L> make_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc) {
+  NttC<L> c;
+  for (int j = 0; j < Digits<L>::D; j++) c.qd[j] = dc.qd[j];
+  c.qinvd = dc.qinvd;
+  u64 carry = 0;
+  for (int j = 0; j < L; j++) {
+    c.q[j] = f.q[j];
+    u64 d = ((u64)f.q[j] << 1) + carry;  // 2q limb by limb (q < 2^(32L-4): no overflow)
+    c.q2[j] = (u32)d;
+    carry = d >> 32;
+    c.nscale[j] = nc ? nc->nscale_m[j] : 0;
+  }
+  c.qinv = f.qinv;
+  return c;
+}
+
+template <int L, int R, bool MUL>
+int launch_pass_LRM(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
+  size_t lds = (size_t)L * ((size_t)1 << (a.k + a.logc)) * sizeof(u32);
+  static bool attr_set = false;
+  if (lds > 65536 && !attr_set) {
+    (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R, MUL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((ntt_pass_kernel<L, R, MUL>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
+  return (int)hipGetLastError();
+}
+
+template <int L, int R>
+int launch_pass_LR(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
+  return a.in2 ? launch_pass_LRM<L, R, true>(c, a, threads, tiles, s)
+               : launch_pass_LRM<L, R, false>(c, a, threads, tiles, s);
+}
+
+template <int L>
+int launch_pass_L(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& nc,
+                  uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s) {
+  NttC<L> c = make_consts<L>(f, dc, &nc);
+  // register blocking is limited by the VGPR budget: 2^r elements of L limbs
+  if (radix_log == 1) return launch_pass_LR<L, 1>(c, a, threads, tiles, s);
+  if constexpr (L <= kMaxLimbsRadix4) {
+    if (radix_log == 2) return launch_pass_LR<L, 2>(c, a, threads, tiles, s);
+  }
+  if constexpr (L <= kMaxLimbsRadix8) {
+    if (radix_log == 3) return launch_pass_LR<L, 3>(c, a, threads, tiles, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+template <int L, int R>
+int launch_batch_LR(bool mul, uint32_t threads, size_t lds, uint32_t grid, const NttPassArgs* d_passes,
+                    const void* d_consts, const uint2* d_items, uint32_t nitems, hipStream_t s) {
+  if (mul)
+    hipLaunchKernelGGL((ntt_batch_kernel<L, R, true>), dim3(grid), dim3(threads), lds, s, d_passes,
+                       (const NttC<L>*)d_consts, d_items, nitems);
+  else
+    hipLaunchKernelGGL((ntt_batch_kernel<L, R, false>), dim3(grid), dim3(threads), lds, s, d_passes,
+                       (const NttC<L>*)d_consts, d_items, nitems);
+  return (int)hipGetLastError();
+}
+
+template <int L>
+int launch_batch_L(uint32_t radix_log, bool mul, uint32_t threads, size_t lds, uint32_t grid,
+                   const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
+                   hipStream_t s) {
+  if (radix_log == 1) return launch_batch_LR<L, 1>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  if constexpr (L <= kMaxLimbsRadix4) {
+    if (radix_log == 2)
+      return launch_batch_LR<L, 2>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  }
+  if constexpr (L <= kMaxLimbsRadix8) {
+    if (radix_log == 3)
+      return launch_batch_LR<L, 3>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+// allow the batch kernels more than 64 KiB of dynamic LDS; called before graph
+// capture so that nothing but launches is recorded
+template <int L, int R>
+void batch_attr_LR() {
+  (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+}
+
+template <int L>
+void batch_attr_L(uint32_t radix_log) {
+  if (radix_log == 1) batch_attr_LR<L, 1>();
+  if constexpr (L <= kMaxLimbsRadix4) {
+    if (radix_log == 2) batch_attr_LR<L, 2>();
+  }
+  if constexpr (L <= kMaxLimbsRadix8) {
+    if (radix_log == 3) batch_attr_LR<L, 3>();
+  }
+}
+
+template <int L>
+int launch_tw_L(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t n, uint32_t logn,
+                       const uint32_t* d_ladder, hipStream_t s) {
+  NttC<L> c = make_consts<L>(f, dc, nullptr);
+  // the ladder buffer carries one_m and then adj after the logn ladder entries
+  const u32* one_m = d_ladder + (size_t)logn * L;
+  const u32* adj = one_m + L;
+  u64 blocks = (n + 255) / 256;
+  hipLaunchKernelGGL((twiddle_kernel<L>), dim3((unsigned)blocks), dim3(256), 0, s, tw, n, logn, d_ladder, c, one_m,
+                     adj);
+  return (int)hipGetLastError();
+}
+
+// the per-limb-count entry points, instantiated once (in ntt_inst_*.hip)
+#define MOMA_NTT_DECLARE(PREFIX, LL)                                                                              \
+  PREFIX template int launch_pass_L<LL>(const FieldRaw&, const DigitConsts&, const NttPassArgs&, const NttConsts&, \
+                                        uint32_t, uint64_t, uint32_t, hipStream_t);                                 \
+  PREFIX template int launch_batch_L<LL>(uint32_t, bool, uint32_t, size_t, uint32_t, const NttPassArgs*,           \
+                                         const void*, const uint2*, uint32_t, hipStream_t);                         \
+  PREFIX template void batch_attr_L<LL>(uint32_t);                                                                  \
+  PREFIX template int launch_tw_L<LL>(const FieldRaw&, const DigitConsts&, uint32_t*, uint64_t, uint32_t,          \
+                                      const uint32_t*, hipStream_t);
+#define MOMA_NTT_INSTANTIATE(LL) MOMA_NTT_DECLARE(, LL)
+#define MOMA_NTT_EXTERN(LL) MOMA_NTT_DECLARE(extern, LL)
+
+}  // namespace moma

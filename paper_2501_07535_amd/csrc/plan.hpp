@@ -34,7 +34,9 @@ struct NttPlan {
   uint32_t logn = 0;
   DirTables fwd, inv;
   NttConsts inv_consts;
-  uint32_t* scratch = nullptr;  // for in-place multi-pass calls
+  NttConsts mul_consts;           // inverse after a fused pointwise product: n^-1 2^(bD) 2^(32L) mod q
+  uint32_t* scratch = nullptr;    // for in-place multi-pass calls
+  uint32_t* spectra = nullptr;    // 2 x n x L words: the two forward transforms of a cyclic product
   NttSchedule sched;
   std::vector<NttPass> passes;
   std::mutex mu;  // guards scratch allocation and schedule changes
@@ -44,6 +46,7 @@ struct NttPlan {
     (void)hipFree(inv.tw);
     (void)hipFree(inv.ladder);
     (void)hipFree(scratch);
+    (void)hipFree(spectra);
   }
 };
 
@@ -57,6 +60,7 @@ uint32_t max_radix_log(int L);
 int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out);
 NttSchedule default_schedule(int L, uint32_t logn);
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s);
+int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s);
 // tuner (tune.cpp)
 std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn);
 bool tune_db_best(const std::string& dev, int L, uint32_t logn, NttSchedule* out);

@@ -126,4 +126,15 @@ def test_ntt_rejects_bad_arguments(case):
         return
     assert lib.moma_ntt_fwd(*args, L, DUMMY, DUMMY, None) == want
     assert lib.moma_ntt_inv(*args, L, DUMMY, DUMMY, None) == want
+    assert lib.moma_ntt_cyclic_mul(*args, L, DUMMY, DUMMY, DUMMY, None) == want
     assert lib.moma_ntt_prepare(*args, L) == want
+
+
+def test_cyclic_mul_rejects_null_buffers():
+    import moma_inputs as mi
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    f = mi.find_prime(256, 0)
+    q, w = _w(f.q, 8), _w(f.root(64), 8)
+    for bufs in ((None, DUMMY, DUMMY), (DUMMY, None, DUMMY), (DUMMY, DUMMY, None)):
+        assert lib.moma_ntt_cyclic_mul(q, w, 64, 8, *bufs, None) == moma.MOMA_E_ARG
