@@ -275,17 +275,22 @@ def cyclic_product(moma, torch, stream, da, db, dc, q, w, n, warmup, reps):
         moma.vmul(ta, tb, q, out=ta)
         moma.ntt_inv(ta, q, w, out=dc)
 
-    res = {}
-    for name, fn in (("fused_us", fused), ("unfused_us", unfused)):
+    for fn in (fused, unfused):
         for _ in range(warmup):
             fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        res[name] = round(e0.elapsed_time(e1) * 1e3 / reps, 3)
+    # alternate the two in rounds so that clock and power drift hit both alike
+    rounds, per = 5, max(1, reps // 5)
+    times = {"fused_us": [], "unfused_us": []}
+    for _ in range(rounds):
+        for name, fn in (("fused_us", fused), ("unfused_us", unfused)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(per):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[name].append(e0.elapsed_time(e1) * 1e3 / per)
+    res = {k: round(float(np.median(v)), 3) for k, v in times.items()}
     s = 12345 % n
     shift = torch.zeros_like(da)
     shift[0, s] = 1

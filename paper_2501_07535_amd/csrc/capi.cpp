@@ -35,6 +35,16 @@ int hip_fail(int e, const char* what) {
 std::mutex g_mu;
 static std::map<std::vector<uint32_t>, std::shared_ptr<FieldEntry>> g_fields;
 
+// v (< 2^(bD)) as the D b-bit digits of the transform's digit form
+static void digits_of(const HBig& v, int L, uint32_t* out) {
+  int b = digit_bits(L), D = digit_count(L);
+  for (int i = 0; i < D; i++) {
+    uint32_t w[2] = {0, 0};
+    HBig::shr(v, b * i).to_limbs(w, 2);
+    out[i] = w[0] & ((1u << b) - 1);
+  }
+}
+
 int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* out) {
   if (!q) return set_error(MOMA_E_ARG, "q is NULL");
   if (limbs < MOMA_MIN_LIMBS || limbs > MOMA_MAX_LIMBS)
@@ -77,14 +87,10 @@ int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* 
     DigitConsts& dc = fe->dc;
     memset(&dc, 0, sizeof(dc));
     int b = digit_bits(f.L), D = digit_count(f.L);
-    for (int i = 0; i < D; i++) {
-      HBig di = HBig::shr(Q, b * i);
-      uint32_t w[2] = {0, 0};
-      di.to_limbs(w, 2);
-      dc.qd[i] = w[0] & ((1u << b) - 1);
-    }
+    digits_of(Q, f.L, dc.qd);
     dc.qinvd = f.qinv & ((1u << b) - 1);
-    HBig::mod(HBig::pow2(b * D), Q).to_limbs(dc.adj, kMaxLimbs);
+    fe->adj = HBig::mod(HBig::pow2(b * D), Q);
+    fe->adj.to_limbs(dc.adj, kMaxLimbs);
   }
   fe->Q = Q;
   fe->one_m = one_m;
@@ -262,15 +268,15 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   if (check_planes(*p)) return set_error(MOMA_E_UNSUPPORTED, "no valid pass split for this size");
   HBig Winv = HBig::powmod(W, HBig(n - 1), Q);
   HBig ninv = HBig::sub(Q, nq);  // n * (q - (q-1)/n) == 1 mod q
-  HBig nscale = HBig::mulmod(ninv, fe->one_m, Q);
+  // last-pass scales in digit Montgomery form (R = 2^(bD)): n^-1 R for the
+  // inverse; n^-1 R^2 after the fused pointwise product of a cyclic product,
+  // which leaves a factor R^-1
+  const HBig& rd = fe->adj;
+  HBig nscale = HBig::mulmod(ninv, rd, Q);
   memset(&p->inv_consts, 0, sizeof(p->inv_consts));
-  nscale.to_limbs(p->inv_consts.nscale_m, kMaxLimbs);
-  // the fused pointwise product of a cyclic product leaves a factor 2^(-bD)
-  // (digit-form Montgomery): its last pass scales by n^-1 2^(bD) instead
-  const int Lc = fe->f.L;
-  HBig rd = HBig::powmod(HBig(2), HBig((uint64_t)digit_bits(Lc) * (uint64_t)digit_count(Lc)), Q);
+  digits_of(nscale, fe->f.L, p->inv_consts.nscale_d);
   memset(&p->mul_consts, 0, sizeof(p->mul_consts));
-  HBig::mulmod(nscale, rd, Q).to_limbs(p->mul_consts.nscale_m, kMaxLimbs);
+  digits_of(HBig::mulmod(nscale, rd, Q), fe->f.L, p->mul_consts.nscale_d);
   rc = build_tables(*p, W, &p->fwd);
   if (rc) return rc;
   rc = build_tables(*p, Winv, &p->inv);

@@ -50,9 +50,9 @@ struct NttPass {
 
 struct NttPassArgs {
   const uint32_t* in;
-  const uint32_t* in2;  // first pass only: multiply in by in2 pointwise while loading (Montgomery, NULL = off)
+  const uint32_t* in2;  // first inverse pass of a cyclic product: multiply by in2 pointwise while loading, else NULL
   uint32_t* out;
-  const uint32_t* tw;  // twiddle table, element-major, L words per entry
+  const uint32_t* tw;  // twiddle table, element-major, digit_stride(L) words per entry
   uint64_t n;
   uint32_t logn, K, k, logc;
   uint32_t last;       // last pass: store canonical residues in [0, q)
@@ -67,7 +67,9 @@ struct NttSchedule {
 };
 
 struct NttConsts {
-  uint32_t nscale_m[kMaxLimbs];  // n^{-1} * 2^(32L) mod q (times 2^(bD) after a fused pointwise product)
+  // last-pass scale of the inverse transform, as D b-bit digits: n^{-1} 2^(bD)
+  // mod q (times another 2^(bD) after a fused pointwise product)
+  uint32_t nscale_d[40];
 };
 
 // per-modulus constants of the digit-form multiply

@@ -41,7 +41,7 @@ struct NttC {
   u32 q[L];
   u32 q2[L];                    // 2q
   u32 qinv;
-  u32 nscale[L];                // n^-1 in Montgomery form (inverse transform, last pass)
+  u32 nscaled[Digits<L>::D];    // last-pass scale of the inverse, digit Montgomery form
   u32 qd[Digits<L>::D];         // q in b-bit digits (twiddle multiply)
   u32 qinvd;                    // -q^-1 mod 2^b
 };
@@ -291,7 +291,7 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
     if (a.last) {
       u32 y[L];
       if (a.scale) {
-        mont_mul_lazy<L>(y, x, c.nscale, c.q, c.qinv);  // x < 4q, nscale < q: y in [0, 2q)
+        mont_mul_digits<L>(y, x, c.nscaled, c.qd, c.qinvd);  // x < 4q, scale < q: y in [0, 2q)
       } else {
         reduce_once<L>(y, x, c.q2);                      // [0, 4q) -> [0, 2q)
       }
@@ -445,8 +445,8 @@ inline NttC<L> make_consts(const FieldRaw& f, const DigitConsts& dc, const NttCo
     u64 d = ((u64)f.q[j] << 1) + carry;  // 2q limb by limb (q < 2^(32L-4): no overflow)
     c.q2[j] = (u32)d;
     carry = d >> 32;
-    c.nscale[j] = nc ? nc->nscale_m[j] : 0;
   }
+  for (int j = 0; j < Digits<L>::D; j++) c.nscaled[j] = nc ? nc->nscale_d[j] : 0;
   c.qinv = f.qinv;
   return c;
 }

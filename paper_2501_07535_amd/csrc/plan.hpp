@@ -17,6 +17,7 @@ struct FieldEntry {
   FieldRaw f;
   DigitConsts dc;
   HBig Q, one_m;
+  HBig adj;  // 2^(bD) mod q: R of the digit form
   // last axpy scalar, cached with its Montgomery form
   std::vector<uint32_t> alpha_key;
   std::vector<uint32_t> alpha_m;
@@ -34,7 +35,7 @@ struct NttPlan {
   uint32_t logn = 0;
   DirTables fwd, inv;
   NttConsts inv_consts;
-  NttConsts mul_consts;           // inverse after a fused pointwise product: n^-1 2^(bD) 2^(32L) mod q
+  NttConsts mul_consts;           // inverse after a fused pointwise product
   uint32_t* scratch = nullptr;    // for in-place multi-pass calls
   uint32_t* spectra = nullptr;    // 2 x n x L words: the two forward transforms of a cyclic product
   NttSchedule sched;
