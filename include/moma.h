@@ -111,7 +111,9 @@ int moma_ntt_inv(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t 
  * Cyclic product of two polynomials of n coefficients (the use of the NTT in
  * Section 2.3, via the convolution theorem):
  *   d_out[k] = sum over i + j == k (mod n) of d_a[i] * d_b[j]  mod q,
- * that is a * b mod (x^n - 1).  Same arguments and preconditions as
+ * that is a * b mod (x^n - 1).  The full product of two polynomials of
+ * degree < n/2 (Section 2.3) is this product of their zero-padded
+ * coefficient vectors.  Same arguments and preconditions as
  * moma_ntt_fwd; omega is a primitive n-th root (any one gives the same
  * result).  Runs fwd(a), fwd(b) and the inverse transform, whose first pass
  * multiplies the two spectra pointwise as it loads them: no separate

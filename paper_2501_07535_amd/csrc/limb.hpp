@@ -325,6 +325,21 @@ __device__ __forceinline__ void ct_butterfly_lazy(u32* x, u32* y, const u32* w, 
   add_vs<L>(y, d, q2);
 }
 
+// Lazy butterfly with twiddle 1 (the first stages of a transform): the same
+// residues as the multiplying butterfly, with t = y mod 2q in [0, 2q) in place
+// of the Montgomery product w*y.
+template <int L>
+__device__ __forceinline__ void ct_butterfly_one(u32* x, u32* y, const u32* q2v) {
+  u32 xr[L], t[L], d[L], s[L];
+  u64 br = sub_vv<L>(s, x, q2v);
+  select<L>(xr, br, x, s);
+  br = sub_vv<L>(s, y, q2v);
+  select<L>(t, br, y, s);
+  add_vv<L>(x, xr, t);
+  sub_vv<L>(d, xr, t);
+  add_vv<L>(y, d, q2v);
+}
+
 // Lazy butterfly with the twiddle in digit form (mont_mul_digits) and 2q in VGPRs.
 template <int L>
 __device__ __forceinline__ void ct_butterfly_digits(u32* x, u32* y, const u32* wd, const u32* qd, u32 qinvd,

@@ -99,7 +99,11 @@ __device__ __forceinline__ u64 tw_pos(const TileGeo& t, u32 sg, u32 lb, u32 g) {
 }
 
 // One round of R stages [sg0, sg0+R) on every radix-2^R unit of the tile.
-template <int L, int R>
+// FIRST: the transform's first round (first pass, sg0 = 0).  There every unit
+// lies in block 0, so a pair whose local block index is 0 has twiddle
+// w^0 = 1 (table entry 2^s) and skips the multiply: all pairs of stage 0, half
+// of stage 1, a quarter of stage 2.
+template <int L, int R, bool FIRST>
 __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, const u32* __restrict__ tw,
                                           const NttC<L>& c) {
   const u32 k = t.k;
@@ -124,10 +128,14 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
       for (int p = 0; p < (1 << (R - 1)); p++) {
         // p with a zero bit inserted at position kb: the pair (e, e + half) of this stage
         const int e = ((p >> kb) << (kb + 1)) | (p & (half - 1));
-        u32 lbk = (lb << s) + (u32)(e >> (R - s));
-        u32 w[digit_stride(L)];
-        load_digits<L>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L));
-        ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
+        if (FIRST && (e >> (R - s)) == 0) {
+          ct_butterfly_one<L>(x[e], x[e + half], q2v);
+        } else {
+          u32 lbk = (lb << s) + (u32)(e >> (R - s));
+          u32 w[digit_stride(L)];
+          load_digits<L>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L));
+          ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
+        }
       }
     }
 #pragma unroll
@@ -141,6 +149,15 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
 // One tile of one pass: stages [K, K+k) on C = 2^logc groups of 2^k elements.
 // LDS holds the tile limb-planar: word (j * 2^k + u) * C + g is limb j of row u
 // of group g, so lanes with consecutive g touch consecutive banks.
+template <int L, int R>
+__device__ __forceinline__ void round_at(u32* lds, const TileGeo& t, u32 sg0, const u32* __restrict__ tw,
+                                         const NttC<L>& c) {
+  if (t.K == 0 && sg0 == 0)
+    ntt_round<L, R, true>(lds, t, sg0, tw, c);
+  else
+    ntt_round<L, R, false>(lds, t, sg0, tw, c);
+}
+
 // Fused pointwise product of a cyclic product's first inverse pass:
 // r = x * y * 2^(-bD) mod q in [0, 2q) for x, y < q (the digit-form multiply
 // with y converted to digits; the last pass's scale constant carries 2^(bD)).
@@ -273,13 +290,13 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
   while (sg < t.k) {
     u32 rem = t.k - sg;
     if (R >= 3 && rem >= 3) {
-      ntt_round<L, (R >= 3 ? 3 : 1)>(lds, t, sg, a.tw, c);
+      round_at<L, (R >= 3 ? 3 : 1)>(lds, t, sg, a.tw, c);
       sg += (R >= 3 ? 3 : 1);
     } else if (R >= 2 && rem >= 2) {
-      ntt_round<L, (R >= 2 ? 2 : 1)>(lds, t, sg, a.tw, c);
+      round_at<L, (R >= 2 ? 2 : 1)>(lds, t, sg, a.tw, c);
       sg += (R >= 2 ? 2 : 1);
     } else {
-      ntt_round<L, 1>(lds, t, sg, a.tw, c);
+      round_at<L, 1>(lds, t, sg, a.tw, c);
       sg += 1;
     }
     __syncthreads();

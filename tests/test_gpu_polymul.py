@@ -37,6 +37,25 @@ def test_cyclic_mul_matches_definition(lam, logn):
     assert (c == oracle.cyclic_conv(f.q, L, a, b)).all()
 
 
+@pytest.mark.parametrize("lam,logn", [(256, 7), (1024, 6)])
+def test_full_polynomial_product_by_zero_padding(lam, logn):
+    """The paper's polynomial product (Section 2.3), sum_i a_i b_{j-i} x^j up to
+    degree 2m-2, from the cyclic product of length n = 2m of the zero-padded
+    coefficient vectors, against that sum in Python integers."""
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(lam, 0)
+    L, n, q = f.limbs, 1 << logn, f.q
+    m = n // 2
+    a, b = mi.residues(f, n, L, 407, 1), mi.residues(f, n, L, 407, 2)
+    a[m:] = 0
+    b[m:] = 0
+    say(f"full product lam={lam} logn={logn}")
+    c = mi.rows_to_ints(from_dev(moma.ntt_cyclic_mul(to_dev(a), to_dev(b), q, f.root(n))))
+    ai, bi = mi.rows_to_ints(a), mi.rows_to_ints(b)
+    want = [sum(ai[i] * bi[j - i] for i in range(max(0, j - m + 1), min(j, m - 1) + 1)) % q for j in range(2 * m - 1)]
+    assert c[:2 * m - 1] == want and c[2 * m - 1] == 0
+
+
 @pytest.mark.parametrize("lam,logn", [(256, 12), (256, 13), (256, 16), (64, 15), (128, 14), (384, 13),
                                       (768, 12), (1024, 11)])
 def test_cyclic_mul_multi_pass(lam, logn):
