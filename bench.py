@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line, print one JSON line per size of the transform sweep "
                          "(2^16..2^24 at 256 bits, 2^20 at 128/384/1024 bits)")
+    ap.add_argument("--blas", action="store_true",
+                    help="instead of the headline line, print one JSON line per modular BLAS op and width "
+                         "(vadd/vsub/vmul/axpy at n=2^24, 256/384/768 bits)")
+    ap.add_argument("--blas-logn", type=int, default=24)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -104,6 +108,70 @@ def sweep(args):
         moma.shutdown()
 
 
+def blas_ops(op: str, L: int) -> int:
+    """Algorithmic integer ops per element: a modular add or subtract is 3L
+    add-class ops (add, trial subtract, select); a modular multiply is
+    3 P(L) + 3L (P(L) word products, two accumulate ops per product, one
+    correction); axpy adds a modular add."""
+    P = word_products(L)
+    return {"vadd": 3 * L, "vsub": 3 * L, "vmul": 3 * P + 3 * L, "axpy": 3 * P + 6 * L}[op]
+
+
+def blas(args):
+    """One line per (op, width): time per call with inputs resident, achieved
+    GB/s and integer op rate, the binding roofline, and outputs checked at
+    sampled indices against the oracle."""
+    import torch
+
+    import oracle
+    import paper_2501_07535_amd as moma
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n = 1 << args.blas_logn
+    idx = np.array([0, 1, n // 3, n // 2 + 7, n - 2, n - 1], dtype=np.int64)
+    for lam in (256, 384, 768):
+        f = mi.find_prime(lam, 0)
+        L, q = f.limbs, f.q
+        da = torch.from_numpy(mi.to_planar(mi.residues(f, n, L, 1, 1)).view(np.int32)).to(dev)
+        db = torch.from_numpy(mi.to_planar(mi.residues(f, n, L, 1, 2)).view(np.int32)).to(dev)
+        dc = torch.empty_like(da)
+        alpha = mi.scalar_residue(f, 1, 3)
+        calls = {"vadd": lambda: moma.vadd(da, db, q, out=dc), "vsub": lambda: moma.vsub(da, db, q, out=dc),
+                 "vmul": lambda: moma.vmul(da, db, q, out=dc), "axpy": lambda: moma.axpy(alpha, da, db, q, out=dc)}
+        # vmul: the autotuner picks schoolbook or Karatsuba products for this width
+        tuned = moma.vmul_tune(q, L, n, reps=5)
+        for op, fn in calls.items():
+            for _ in range(args.warmup):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / args.steps
+            sel = torch.from_numpy(idx).to(dev)
+            a = mi.from_planar(da[:, sel].cpu().numpy().view(np.uint32))
+            bb = mi.from_planar(db[:, sel].cpu().numpy().view(np.uint32))
+            got = mi.from_planar(dc[:, sel].cpu().numpy().view(np.uint32))
+            want = {"vadd": lambda: oracle.vadd(q, L, a, bb), "vsub": lambda: oracle.vsub(q, L, a, bb),
+                    "vmul": lambda: oracle.vmul(q, L, a, bb), "axpy": lambda: oracle.axpy(q, L, alpha, a, bb)}[op]()
+            byt = 3 * n * 4 * L
+            ops = blas_ops(op, L) * n
+            t_hbm, t_alu = byt / PEAK_HBM, ops / PEAK_INT_OPS
+            bound = "hbm" if t_hbm >= t_alu else "alu"
+            print(json.dumps({"op": op, "lambda": lam, "limbs": L, "log2_n": args.blas_logn, "us": round(us, 2),
+                              "GB_s": round(byt / us / 1e3, 1), "Tops_s": round(ops / us / 1e6, 3),
+                              "bound": bound, "roofline_us": round(max(t_hbm, t_alu) * 1e6, 2),
+                              "frac": round(max(t_hbm, t_alu) * 1e6 / us, 4),
+                              "hbm_frac": round(t_hbm * 1e6 / us, 4), "alu_frac": round(t_alu * 1e6 / us, 4),
+                              "vmul_variants": tuned if op == "vmul" else None,
+                              "sampled_vs_oracle": bool((got == want).all())}), flush=True)
+        del da, db, dc
+        torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -112,6 +180,9 @@ def main():
         sys.exit(2)
     if args.sweep:
         sweep(args)
+        return
+    if args.blas:
+        blas(args)
         return
     import torch
 

@@ -21,8 +21,13 @@
  *   undefined (but memory-safe) results.
  *
  * Preconditions checked on the host before anything is enqueued
- *   2 <= limbs <= 32; q odd, q >= 3, bitlen(q) <= 32*limbs - 4 (the paper's
- *   moduli are four bits short of the class width, Section 5.2);
+ *   2 <= limbs <= 32; q odd, q >= 3, bitlen(q) <= 32*limbs.  The paper's
+ *   moduli are four bits short of the class width (Section 5.2), which
+ *   leaves headroom for lazy reduction; a modulus within 4 bits of the
+ *   storage width ("full width") computes in one more internal limb, and the
+ *   transforms stage such vectors through library-owned buffers of that
+ *   width (one extra copy in and out).  A full-width 1024-bit modulus would
+ *   need 33 internal limbs and is MOMA_E_UNSUPPORTED;
  *   n a power of two, 2 <= n <= 2^26 (BLAS: any n >= 0);
  *   omega of multiplicative order exactly n (omega^{n/2} == q - 1), which
  *   also implies n | q - 1 for prime q.  Primality of q is the caller's
@@ -91,6 +96,27 @@ int moma_vmul(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a
               uint32_t* d_out, void* stream);
 int moma_axpy(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* alpha, const uint32_t* d_x,
               const uint32_t* d_y, uint32_t* d_out, void* stream);
+
+/*
+ * vmul's word-product variant, per compute limb count (Eq. (mulk)): the two
+ * full L x L products of the Barrett multiply by schoolbook product scanning
+ * (L^2 word products each) or by one level of Karatsuba (3 ceil(L/2)^2 plus
+ * the additions).  Both give the same result, bit for bit; which is faster
+ * depends on the width, so it is an autotuner choice.
+ *   moma_vmul_set_variant / moma_vmul_get_variant: the variant used by later
+ *     moma_vmul calls whose modulus has the same compute limb count
+ *     (MOMA_E_UNSUPPORTED for Karatsuba below 2 compute limbs);
+ *   moma_vmul_tune: times each variant on n zero residues (median of reps
+ *     runs after one warm-up; reps 0 means 5), installs the faster, writes the
+ *     two times in microseconds to us_out[2] (us_out[1] = 0 when only
+ *     schoolbook applies) and the choice to *chosen (may be NULL).  Allocates
+ *     3 n L words for the duration of the call and synchronises.
+ * The setting is process-wide and survives moma_shutdown.
+ */
+enum moma_vmul_variant { MOMA_VMUL_SCHOOLBOOK = 0, MOMA_VMUL_KARATSUBA = 1 };
+int moma_vmul_set_variant(const uint32_t* q, uint32_t limbs, uint32_t variant);
+int moma_vmul_get_variant(const uint32_t* q, uint32_t limbs, uint32_t* variant);
+int moma_vmul_tune(const uint32_t* q, uint32_t limbs, uint64_t n, uint32_t reps, float* us_out, uint32_t* chosen);
 
 /*
  * Number theoretic transform, Eq. (ntt): natural order in, natural order out.

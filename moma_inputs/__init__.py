@@ -135,7 +135,7 @@ def is_probable_prime(n: int) -> bool:
 class Field:
     """A prime field Z_q for one bit-width class ``lam``."""
     lam: int       # bit-width class (64, 96, ..., 1024)
-    q: int         # the prime, bitlen(q) == lam - 4, 2**32 | q - 1
+    q: int         # the prime, bitlen(q) == lam - 4 (lam for a full-width one), 2**32 | q - 1
     z: int         # least quadratic non-residue
 
     @property
@@ -165,17 +165,18 @@ class Field:
         return int_to_limbs(v, L)
 
 
-def find_prime(lam: int, *ids: int) -> Field:
-    """Seeded NTT-friendly prime of exactly lam-4 bits: q = c*2**32 + 1.
+def find_prime(lam: int, *ids: int, bits: int | None = None) -> Field:
+    """Seeded NTT-friendly prime of exactly M = lam-4 bits (or `bits`, e.g. lam
+    for a full-width modulus): q = c*2**32 + 1.
 
     c is drawn with exactly M-32 bits (top bit set), then incremented (wrapping
     inside its range) until q passes Miller-Rabin; the first hit is taken.
     """
-    M = lam - 4
+    M = lam - 4 if bits is None else bits
     cb = M - 32
     if cb < 2:
         raise ValueError("class too small for c*2**32+1 primes")
-    key = stream_key(P_PRIME, lam, *ids)
+    key = stream_key(P_PRIME, lam, *ids) if bits is None else stream_key(P_PRIME, lam, *ids, 1 << 20, M)
     words = (cb + 63) // 64
     r = 0
     for i in range(words):

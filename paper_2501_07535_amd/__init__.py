@@ -54,6 +54,10 @@ _lib.moma_axpy.restype = ctypes.c_int
 for _name in ("moma_ntt_fwd", "moma_ntt_inv"):
     getattr(_lib, _name).argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
     getattr(_lib, _name).restype = ctypes.c_int
+_lib.moma_vmul_set_variant.argtypes = [_u32p, ctypes.c_uint32, ctypes.c_uint32]
+_lib.moma_vmul_get_variant.argtypes = [_u32p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+_lib.moma_vmul_tune.argtypes = [_u32p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_uint32)]
 _lib.moma_ntt_cyclic_mul.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp, _vp]
 _lib.moma_ntt_cyclic_mul.restype = ctypes.c_int
 _lib.moma_ntt_prepare.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32]
@@ -147,7 +151,7 @@ _lib.moma_shutdown.restype = None
 MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
-            "moma_axpy", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_cyclic_mul", "moma_ntt_prepare", "moma_ntt_describe",
+            "moma_axpy", "moma_vmul_set_variant", "moma_vmul_get_variant", "moma_vmul_tune", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_cyclic_mul", "moma_ntt_prepare", "moma_ntt_describe",
             "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_ntt_default_schedule", "moma_batch_create", "moma_batch_run",
             "moma_batch_info", "moma_batch_destroy", "moma_ntt_tune", "moma_ntt_candidates", "moma_tune_db_count",
             "moma_tune_db_get", "moma_tune_db_clear", "moma_tune_db_save", "moma_tune_db_load",
@@ -248,6 +252,28 @@ def axpy(alpha: int, x, y, q: int, out=None, stream=None):
     _check(_lib.moma_axpy(_words(q, limbs), limbs, n, _words(alpha, limbs), x.data_ptr(), y.data_ptr(),
                           out.data_ptr(), _stream(stream)))
     return out
+
+
+VMUL_SCHOOLBOOK, VMUL_KARATSUBA = 0, 1
+
+
+def vmul_set_variant(q: int, limbs: int, variant: int):
+    """Word-product variant of vmul for moduli with q's compute limb count."""
+    _check(_lib.moma_vmul_set_variant(_words(q, limbs), limbs, variant))
+
+
+def vmul_get_variant(q: int, limbs: int) -> int:
+    v = ctypes.c_uint32(0)
+    _check(_lib.moma_vmul_get_variant(_words(q, limbs), limbs, ctypes.byref(v)))
+    return int(v.value)
+
+
+def vmul_tune(q: int, limbs: int, n: int, reps: int = 5) -> dict:
+    """Time schoolbook and Karatsuba vmul on n elements and install the faster."""
+    us = (ctypes.c_float * 2)()
+    ch = ctypes.c_uint32(0)
+    _check(_lib.moma_vmul_tune(_words(q, limbs), limbs, n, reps, us, ctypes.byref(ch)))
+    return {"schoolbook_us": float(us[0]), "karatsuba_us": float(us[1]) or None, "chosen": int(ch.value)}
 
 
 def ntt_fwd(x, q: int, omega: int, out=None, stream=None):

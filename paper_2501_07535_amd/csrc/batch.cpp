@@ -44,11 +44,21 @@ struct ZeroFill {
   int from, to;
 };
 
+// full-width moduli: a job's Ls storage planes copied into (and back out of)
+// an L-plane stage whose top plane is zero
+struct PlaneCopy {
+  uint32_t* dst;
+  const uint32_t* src;
+  uint64_t words;
+};
+
 struct BatchImpl {
   std::vector<std::shared_ptr<NttPlan>> plans;  // keep tables alive
   std::vector<void*> dev_allocs;
   std::vector<BatchLaunch> launches;
   std::vector<ZeroFill> fills;
+  std::vector<PlaneCopy> copy_in, copy_out;
+  std::vector<ZeroFill> stage_tops;
   uint64_t items = 0;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -140,28 +150,58 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       sched = p->sched;
     }
     const size_t plane_words = (size_t)p->n * f.L;
-    if (job.kind == MOMA_JOB_CYCLIC_MUL) {
+    const bool full = f.Ls < f.L;
+    auto alloc = [&](size_t words, uint32_t** outp) -> int {
       void* s = nullptr;
-      if (hipMalloc(&s, 2 * plane_words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, tag + "spectra");
+      if (hipMalloc(&s, words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, tag + "job buffers");
       b.dev_allocs.push_back(s);
-      uint32_t* sa = (uint32_t*)s;
+      *outp = (uint32_t*)s;
+      return MOMA_OK;
+    };
+    // a full-width job reads its input from an L-plane stage
+    auto staged = [&](const uint32_t* src, const uint32_t** outp) -> int {
+      uint32_t* st = nullptr;
+      int r = alloc(plane_words, &st);
+      if (r) return r;
+      b.copy_in.push_back({st, src, p->n * (uint64_t)f.Ls});
+      b.stage_tops.push_back({st, p->n, f.Ls, f.L});
+      *outp = st;
+      return MOMA_OK;
+    };
+    if (job.kind == MOMA_JOB_CYCLIC_MUL) {
+      uint32_t* sa = nullptr;
+      int r = alloc(2 * plane_words, &sa);
       uint32_t* sb = sa + plane_words;
-      add(*p, sched, passes, p->fwd, none, false, job.d_in, nullptr, sa, sa, 0);
-      add(*p, sched, passes, p->fwd, none, false, job.d_in2, nullptr, sb, sb, 0);
-      add(*p, sched, passes, p->inv, p->mul_consts, true, sa, sb, job.d_out, job.d_out, (uint32_t)passes.size());
+      const uint32_t *ina = job.d_in, *inb = job.d_in2;
+      uint32_t* res = job.d_out;
+      if (!r && full) r = staged(job.d_in, &ina);
+      if (!r && full) r = staged(job.d_in2, &inb);
+      if (!r && full) r = alloc(plane_words, &res);
+      if (r) return r;
+      add(*p, sched, passes, p->fwd, none, false, ina, nullptr, sa, sa, 0);
+      add(*p, sched, passes, p->fwd, none, false, inb, nullptr, sb, sb, 0);
+      add(*p, sched, passes, p->inv, p->mul_consts, true, sa, sb, res, res, (uint32_t)passes.size());
+      if (full) b.copy_out.push_back({job.d_out, res, p->n * (uint64_t)f.Ls});
       if (f.Ls > f.L) b.fills.push_back({job.d_out, p->n, f.L, f.Ls});
       continue;
     }
     const bool inverse = job.kind == MOMA_JOB_INVERSE;
-    uint32_t* first_out = job.d_out;
-    if (passes.size() > 1 && job.d_in == job.d_out) {
-      void* s = nullptr;
-      if (hipMalloc(&s, plane_words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, tag + "scratch");
-      b.dev_allocs.push_back(s);
-      first_out = (uint32_t*)s;
+    const uint32_t* in = job.d_in;
+    uint32_t* res = job.d_out;
+    uint32_t* first_out = nullptr;
+    if (full) {
+      int r = staged(job.d_in, &in);
+      if (!r) r = alloc(plane_words, &res);
+      if (r) return r;
+      b.copy_out.push_back({job.d_out, res, p->n * (uint64_t)f.Ls});
     }
-    add(*p, sched, passes, inverse ? p->inv : p->fwd, inverse ? p->inv_consts : none, inverse, job.d_in, nullptr,
-        first_out, job.d_out, 0);
+    first_out = res;
+    if (passes.size() > 1 && in == res) {
+      int r = alloc(plane_words, &first_out);
+      if (r) return r;
+    }
+    add(*p, sched, passes, inverse ? p->inv : p->fwd, inverse ? p->inv_consts : none, inverse, in, nullptr,
+        first_out, res, 0);
     if (f.Ls > f.L && job.d_out != job.d_in) b.fills.push_back({job.d_out, p->n, f.L, f.Ls});
   }
   // upload tables and build the launch list, phase by phase
@@ -209,7 +249,17 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
   if (hipStreamCreate(&b.cap)) return hip_fail(1, "batch stream");
   if (hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal)) return hip_fail(1, "begin capture");
   int err = 0;
+  for (const PlaneCopy& c : b.copy_in) {
+    err = launch_copy_words(c.dst, c.src, c.words, b.cap);
+    if (err) break;
+  }
+  if (!err)
+    for (const ZeroFill& z : b.stage_tops) {
+      err = launch_zero_planes(z.out, z.n, z.from, z.to, b.cap);
+      if (err) break;
+    }
   for (const BatchLaunch& bl : b.launches) {
+    if (err) break;
     err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.threads, bl.lds, bl.grid, bl.d_passes, bl.d_consts,
                            bl.d_items, bl.nitems, b.cap);
     if (err) break;
@@ -217,6 +267,11 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
   if (!err)
     for (const ZeroFill& z : b.fills) {
       err = launch_zero_planes(z.out, z.n, z.from, z.to, b.cap);
+      if (err) break;
+    }
+  if (!err)
+    for (const PlaneCopy& c : b.copy_out) {
+      err = launch_copy_words(c.dst, c.src, c.words, b.cap);
       if (err) break;
     }
   hipError_t ec = hipStreamEndCapture(b.cap, &b.graph);
@@ -258,7 +313,9 @@ int moma_batch_run(moma_batch_t b, void* stream) {
 
 int moma_batch_info(moma_batch_t b, uint32_t* launches, uint64_t* items) {
   if (!b) return set_error(MOMA_E_ARG, "batch is NULL");
-  if (launches) *launches = (uint32_t)(b->impl.launches.size() + b->impl.fills.size());
+  if (launches)
+    *launches = (uint32_t)(b->impl.launches.size() + b->impl.fills.size() + b->impl.copy_in.size() +
+                           b->impl.stage_tops.size() + b->impl.copy_out.size());
   if (items) *items = b->impl.items;
   return MOMA_OK;
 }

@@ -15,32 +15,37 @@ struct BlasC {
   u32 qinv;
   BarrettC<L> bc;
   u32 alpha_m[L];
+  u32 ls;
 };
 
-template <int L, int OP>
+template <int L, int OP, bool KARA>
 __global__ __launch_bounds__(256) void blas_kernel(const u32* __restrict__ pa, const u32* __restrict__ pb,
                                                    u32* __restrict__ pout, u64 n, BlasC<L> c) {
   u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  // a full-width modulus has one storage plane fewer than compute limbs: the
+  // missing top limb of every input is zero, and the result's is zero too
+  const int lim = c.ls < (u32)L ? (int)c.ls : L;
   u32 a[L], b[L], r[L];
 #pragma unroll
   for (int j = 0; j < L; j++) {
-    a[j] = pa[j * n + i];
-    b[j] = pb[j * n + i];
+    a[j] = j < lim ? pa[j * n + i] : 0u;
+    b[j] = j < lim ? pb[j * n + i] : 0u;
   }
   if (OP == OP_VADD) {
     mod_add<L>(r, a, b, c.q);
   } else if (OP == OP_VSUB) {
     mod_sub<L>(r, a, b, c.q);
   } else if (OP == OP_VMUL) {
-    barrett_mul<L>(r, a, b, c.bc);
+    barrett_mul<L, KARA>(r, a, b, c.bc);
   } else {
     u32 t[L];
     mont_mul<L>(t, a, c.alpha_m, c.q, c.qinv);  // alpha * x
     mod_add<L>(r, t, b, c.q);                   // + y
   }
 #pragma unroll
-  for (int j = 0; j < L; j++) pout[j * n + i] = r[j];
+  for (int j = 0; j < L; j++)
+    if (j < lim) pout[j * n + i] = r[j];
 }
 
 // mont_mul takes its second operand from VGPRs; alpha is uniform, so keep a
@@ -56,9 +61,16 @@ static int launch_blas_L(const FieldRaw& f, const BlasArgs& a, hipStream_t s) {
   }
   c.qinv = f.qinv;
   c.bc.d = f.d;
+  c.ls = a.ls;
   const unsigned T = 256;
   u64 blocks = (a.n + T - 1) / T;
-  hipLaunchKernelGGL((blas_kernel<L, OP>), dim3((unsigned)blocks), dim3(T), 0, s, a.a, a.b, a.out, a.n, c);
+  if constexpr (OP == OP_VMUL && L >= 2) {
+    if (a.variant == 1) {
+      hipLaunchKernelGGL((blas_kernel<L, OP, true>), dim3((unsigned)blocks), dim3(T), 0, s, a.a, a.b, a.out, a.n, c);
+      return (int)hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((blas_kernel<L, OP, false>), dim3((unsigned)blocks), dim3(T), 0, s, a.a, a.b, a.out, a.n, c);
   return (int)hipGetLastError();
 }
 
@@ -94,6 +106,22 @@ int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, 
   if (n == 0 || from_plane >= to_plane) return 0;
   u64 blocks = (n + 255) / 256;
   hipLaunchKernelGGL(zero_planes_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out, n, from_plane, to_plane);
+  return (int)hipGetLastError();
+}
+
+}  // namespace moma
+
+namespace moma {
+
+__global__ __launch_bounds__(256) void copy_words_kernel(u32* __restrict__ dst, const u32* __restrict__ src, u64 count) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+
+int launch_copy_words(uint32_t* dst, const uint32_t* src, uint64_t count, hipStream_t s) {
+  if (count == 0) return 0;
+  u64 blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(copy_words_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, count);
   return (int)hipGetLastError();
 }
 

@@ -63,9 +63,14 @@ int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* 
   HBig Q = HBig::from_limbs(q, (int)limbs);
   if (!Q.is_odd() || HBig::cmp(Q, HBig(3)) < 0) return set_error(MOMA_E_MODULUS, "q must be odd and >= 3");
   int M = Q.bitlen();
-  if (M > 32 * (int)limbs - 4)
-    return set_error(MOMA_E_MODULUS, "bitlen(q) = " + std::to_string(M) + " exceeds 32*limbs-4 = " +
-                                         std::to_string(32 * limbs - 4));
+  if (M > 32 * (int)limbs)
+    return set_error(MOMA_E_MODULUS, "bitlen(q) = " + std::to_string(M) + " exceeds 32*limbs = " +
+                                         std::to_string(32 * limbs));
+  // compute limbs keep 4 bits of headroom for the lazy reductions; a modulus
+  // within 4 bits of the storage width (full width) computes in one more limb
+  if ((M + 4 + 31) / 32 > kMaxLimbs)
+    return set_error(MOMA_E_UNSUPPORTED, "a modulus of " + std::to_string(M) + " bits needs " +
+                                             std::to_string((M + 4 + 31) / 32) + " compute limbs (at most 32)");
   FieldRaw& f = fe->f;
   memset(&f, 0, sizeof(f));
   f.L = (M + 4 + 31) / 32;
@@ -324,27 +329,58 @@ static int enqueue_passes(NttPlan& p, const std::vector<NttPass>& passes, const 
   return MOMA_OK;
 }
 
+// lazily allocated per-plan buffer of n x L words (under the plan's mutex)
+static int plan_buffer(NttPlan& p, uint32_t** slot, size_t copies, const char* what) {
+  if (!*slot && hipMalloc((void**)slot, copies * (size_t)p.n * p.fe->f.L * sizeof(uint32_t)))
+    return set_error(MOMA_E_NOMEM, std::string(what) + " allocation failed");
+  return MOMA_OK;
+}
+
+// Full-width modulus (Ls = L - 1 storage planes): copy the Ls planes of src
+// into stage and zero its top plane, so the kernels read L planes.
+static int stage_in(NttPlan& p, uint32_t* stage, const uint32_t* src, hipStream_t s) {
+  const FieldRaw& f = p.fe->f;
+  int e = launch_copy_words(stage, src, p.n * (uint64_t)f.Ls, s);
+  if (!e) e = launch_zero_planes(stage, p.n, f.Ls, f.L, s);
+  return e ? hip_fail(e, "full-width staging") : MOMA_OK;
+}
+
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s) {
   const FieldRaw& f = p.fe->f;
+  const bool full = f.Ls < f.L;
   std::vector<NttPass> passes;
   NttSchedule sched;
   uint32_t* first_out = d_out;
+  uint32_t* stage = nullptr;
   {
     std::lock_guard<std::mutex> lk(p.mu);
     passes = p.passes;
     sched = p.sched;
-    if (passes.size() > 1 && d_in == d_out) {
-      if (!p.scratch) {
-        if (hipMalloc((void**)&p.scratch, (size_t)p.n * f.L * sizeof(uint32_t)))
-          return set_error(MOMA_E_NOMEM, "scratch allocation failed");
-      }
+    if (full) {
+      int rc = plan_buffer(p, &p.stage, 1, "staging");
+      if (rc) return rc;
+      stage = p.stage;
+    }
+    if (passes.size() > 1 && (full || d_in == d_out)) {
+      int rc = plan_buffer(p, &p.scratch, 1, "scratch");
+      if (rc) return rc;
       first_out = p.scratch;
     }
   }
   NttConsts none;
   memset(&none, 0, sizeof(none));
-  int rc = enqueue_passes(p, passes, sched, inverse ? p.inv : p.fwd, inverse ? p.inv_consts : none, inverse, d_in,
-                          nullptr, first_out, d_out, s);
+  const DirTables& t = inverse ? p.inv : p.fwd;
+  const NttConsts& nc = inverse ? p.inv_consts : none;
+  if (full) {
+    // through L planes in place on the stage, then back to the caller's Ls planes
+    int rc = stage_in(p, stage, d_in, s);
+    if (!rc) rc = enqueue_passes(p, passes, sched, t, nc, inverse, stage, nullptr,
+                                 passes.size() > 1 ? first_out : stage, stage, s);
+    if (rc) return rc;
+    int e = launch_copy_words(d_out, stage, p.n * (uint64_t)f.Ls, s);
+    return e ? hip_fail(e, "full-width staging") : MOMA_OK;
+  }
+  int rc = enqueue_passes(p, passes, sched, t, nc, inverse, d_in, nullptr, first_out, d_out, s);
   if (rc) return rc;
   if (f.Ls > f.L && d_out != d_in) {
     int e = launch_zero_planes(d_out, p.n, f.L, f.Ls, s);
@@ -359,24 +395,37 @@ int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hi
 // last pass scales by n^-1 2^(bD), which cancels that factor.
 int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s) {
   const FieldRaw& f = p.fe->f;
+  const bool full = f.Ls < f.L;
   std::vector<NttPass> passes;
   NttSchedule sched;
-  uint32_t* spec = nullptr;
+  uint32_t *spec = nullptr, *stage = nullptr;
   {
     std::lock_guard<std::mutex> lk(p.mu);
     passes = p.passes;
     sched = p.sched;
-    if (!p.spectra) {
-      if (hipMalloc((void**)&p.spectra, 2 * (size_t)p.n * f.L * sizeof(uint32_t)))
-        return set_error(MOMA_E_NOMEM, "spectra allocation failed");
-    }
+    int rc = plan_buffer(p, &p.spectra, 2, "spectra");
+    if (!rc && full) rc = plan_buffer(p, &p.stage, 1, "staging");
+    if (rc) return rc;
     spec = p.spectra;
+    stage = p.stage;
   }
   uint32_t* sa = spec;
   uint32_t* sb = spec + (size_t)p.n * f.L;
   NttConsts none;
   memset(&none, 0, sizeof(none));
-  int rc = enqueue_passes(p, passes, sched, p.fwd, none, false, d_a, nullptr, sa, sa, s);
+  int rc = MOMA_OK;
+  if (full) {
+    // each input through the stage into its spectrum; the product back through the stage
+    rc = stage_in(p, stage, d_a, s);
+    if (!rc) rc = enqueue_passes(p, passes, sched, p.fwd, none, false, stage, nullptr, sa, sa, s);
+    if (!rc) rc = stage_in(p, stage, d_b, s);
+    if (!rc) rc = enqueue_passes(p, passes, sched, p.fwd, none, false, stage, nullptr, sb, sb, s);
+    if (!rc) rc = enqueue_passes(p, passes, sched, p.inv, p.mul_consts, true, sa, sb, stage, stage, s);
+    if (rc) return rc;
+    int e = launch_copy_words(d_out, stage, p.n * (uint64_t)f.Ls, s);
+    return e ? hip_fail(e, "full-width staging") : MOMA_OK;
+  }
+  rc = enqueue_passes(p, passes, sched, p.fwd, none, false, d_a, nullptr, sa, sa, s);
   if (!rc) rc = enqueue_passes(p, passes, sched, p.fwd, none, false, d_b, nullptr, sb, sb, s);
   if (!rc) rc = enqueue_passes(p, passes, sched, p.inv, p.mul_consts, true, sa, sb, d_out, d_out, s);
   if (rc) return rc;
@@ -398,6 +447,10 @@ static int ntt_entry(bool inverse, const uint32_t* q, const uint32_t* omega, uin
 
 // ------------------------------------------------------------------ BLAS
 
+// vmul's product variant per compute limb count (MOMA_VMUL_*), set by
+// moma_vmul_set_variant or moma_vmul_tune; schoolbook until then
+static uint32_t g_vmul_variant[kMaxLimbs + 1];
+
 static int blas_entry(int op, const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* alpha,
                       const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, void* stream) {
   std::shared_ptr<FieldEntry> fe;
@@ -412,6 +465,11 @@ static int blas_entry(int op, const uint32_t* q, uint32_t limbs, uint64_t n, con
   a.b = d_b;
   a.out = d_out;
   a.n = n;
+  a.ls = (uint32_t)fe->f.Ls;
+  if (op == OP_VMUL) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    a.variant = g_vmul_variant[fe->f.L];
+  }
   if (op == OP_AXPY) {
     if (!alpha) return set_error(MOMA_E_ARG, "alpha is NULL");
     std::vector<uint32_t> key(alpha, alpha + limbs);
@@ -476,6 +534,89 @@ int moma_vsub(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a
 int moma_vmul(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_a, const uint32_t* d_b,
               uint32_t* d_out, void* stream) {
   return blas_entry(OP_VMUL, q, limbs, n, nullptr, d_a, d_b, d_out, stream);
+}
+
+int moma_vmul_set_variant(const uint32_t* q, uint32_t limbs, uint32_t variant) {
+  std::shared_ptr<FieldEntry> fe;
+  int rc = build_field(q, limbs, &fe);
+  if (rc) return rc;
+  if (variant > MOMA_VMUL_KARATSUBA) return set_error(MOMA_E_ARG, "unknown vmul variant");
+  if (variant == MOMA_VMUL_KARATSUBA && fe->f.L < 2)
+    return set_error(MOMA_E_UNSUPPORTED, "Karatsuba needs at least 2 compute limbs");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_vmul_variant[fe->f.L] = variant;
+  return MOMA_OK;
+}
+
+int moma_vmul_get_variant(const uint32_t* q, uint32_t limbs, uint32_t* variant) {
+  if (!variant) return set_error(MOMA_E_ARG, "variant is NULL");
+  std::shared_ptr<FieldEntry> fe;
+  int rc = build_field(q, limbs, &fe);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  *variant = g_vmul_variant[fe->f.L];
+  return MOMA_OK;
+}
+
+int moma_vmul_tune(const uint32_t* q, uint32_t limbs, uint64_t n, uint32_t reps, float* us_out, uint32_t* chosen) {
+  if (!us_out) return set_error(MOMA_E_ARG, "us_out is NULL");
+  std::shared_ptr<FieldEntry> fe;
+  int rc = build_field(q, limbs, &fe);
+  if (rc) return rc;
+  if (n == 0 || n > (1ull << 31)) return set_error(MOMA_E_ARG, "n must be in [1, 2^31]");
+  if (reps == 0) reps = 5;
+  const int L = fe->f.L;
+  const uint32_t nvar = L >= 2 ? 2 : 1;
+  // zero residues: the kernels' timing does not depend on the values
+  uint32_t* buf = nullptr;
+  const size_t words = (size_t)n * L;
+  if (hipMalloc((void**)&buf, 3 * words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, "tune buffers");
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int err = (int)hipMemset(buf, 0, 3 * words * sizeof(uint32_t));
+  if (!err) err = (int)hipStreamCreate(&st);
+  if (!err) err = (int)hipEventCreate(&e0);
+  if (!err) err = (int)hipEventCreate(&e1);
+  float best = 0;
+  uint32_t pick = 0;
+  for (uint32_t v = 0; v < nvar && !err; v++) {
+    BlasArgs a;
+    memset(&a, 0, sizeof(a));
+    a.a = buf;
+    a.b = buf + words;
+    a.out = buf + 2 * words;
+    a.n = n;
+    a.variant = v;
+    std::vector<float> t;
+    for (uint32_t r = 0; r < reps + 1 && !err; r++) {
+      err = (int)hipEventRecord(e0, st);
+      if (!err) err = launch_blas(OP_VMUL, fe->f, a, st);
+      if (!err) err = (int)hipEventRecord(e1, st);
+      if (!err) err = (int)hipEventSynchronize(e1);
+      float ms = 0;
+      if (!err) (void)hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) t.push_back(ms * 1e3f);  // the first run warms up
+    }
+    if (err) break;
+    std::sort(t.begin(), t.end());
+    us_out[v] = t[t.size() / 2];
+    if (v == 0 || us_out[v] < best) {
+      best = us_out[v];
+      pick = v;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  (void)hipFree(buf);
+  if (err) return hip_fail(err, "vmul tuning");
+  if (nvar == 1) us_out[1] = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_vmul_variant[L] = pick;
+  }
+  if (chosen) *chosen = pick;
+  return MOMA_OK;
 }
 
 int moma_axpy(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* alpha, const uint32_t* d_x,

@@ -23,7 +23,7 @@ constexpr int kMaxLimbsRadix8 = 5;
 // the first L words of each array into a compile-time sized kernel argument.
 struct FieldRaw {
   int L;                   // compute limbs: ceil((bitlen(q) + 4) / 32)
-  int Ls;                  // storage limbs (planes) given by the caller
+  int Ls;                  // storage limbs (planes) given by the caller; L - 1 for a full-width q
   uint32_t q[kMaxLimbs];
   uint32_t qinv;           // -q^{-1} mod 2^32 (Montgomery)
   uint32_t one_m[kMaxLimbs];  // 2^(32L) mod q (1 in Montgomery form)
@@ -40,6 +40,8 @@ struct BlasArgs {
   uint32_t* out;
   uint64_t n;
   uint32_t alpha_m[kMaxLimbs];  // axpy: alpha * 2^(32L) mod q (Montgomery form)
+  uint32_t variant;              // vmul: 0 schoolbook products, 1 Karatsuba (L >= 2)
+  uint32_t ls;                   // storage planes; fewer than L for a full-width modulus
 };
 
 // One pass of the transform: k radix-2 stages [K, K+k) over tiles of C groups.
@@ -85,6 +87,8 @@ int set_error(int code, const std::string& detail);
 // launchers (return hipError_t as int)
 int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s);
 int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, hipStream_t s);
+// dst[i] = src[i] for i < count (a kernel, so that graph capture records no copy node)
+int launch_copy_words(uint32_t* dst, const uint32_t* src, uint64_t count, hipStream_t s);
 int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& c,
                     uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s);
 // batched transforms: one launch runs items (pass record, tile) of many plans

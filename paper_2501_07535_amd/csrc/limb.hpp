@@ -378,12 +378,81 @@ struct BarrettC {
   u32 d;
 };
 
+// t[0 .. M+N) = a[0 .. M) * b[0 .. N), product scanning, both operands in VGPRs
+template <int M, int N>
+__device__ __forceinline__ void mul_ps(u32* t, const u32* a, const u32* b) {
+  u64 acc = 0;
+  u32 hi = 0;
+#pragma unroll
+  for (int k = 0; k < M + N - 1; k++) {
+#pragma unroll
+    for (int i = (k < N ? 0 : k - N + 1); i <= (k < M ? k : M - 1); i++) mac_vv(acc, hi, a[i], b[k - i]);
+    t[k] = (u32)acc;
+    shift_col(acc, hi);
+  }
+  t[M + N - 1] = (u32)acc;
+}
+
+// t[0 .. 2L) = a * b by one level of Karatsuba (Eq. (mulk)), subtractive form:
+// with a = a1 B^h + a0, b = b1 B^h + b0 (B = 2^32, h = ceil(L/2)),
+//   a b = z2 B^(2h) + (z0 + z2 - s |a0 - a1| |b0 - b1|) B^h + z0,
+//   z0 = a0 b0, z2 = a1 b1, s = sign((a0 - a1)(b0 - b1)).
+// Three half-size products (3 ceil(L/2)^2 word products instead of L^2); the
+// differences need no carry bit, at the price of the sign selects.
+template <int L>
+__device__ __forceinline__ void kara_mul(u32* t, const u32* a, const u32* b) {
+  constexpr int h = (L + 1) / 2, g = L - h;  // a0, b0: h limbs; a1, b1: g <= h limbs
+  u32 z0[2 * h], z2[2 * g], p[2 * h];
+  mul_ps<h, h>(z0, a, b);
+  mul_ps<g, g>(z2, a + h, b + h);
+  u32 a1[h], b1[h], da[h], da2[h], db[h], db2[h];
+#pragma unroll
+  for (int i = 0; i < h; i++) {
+    a1[i] = i < g ? a[h + i] : 0u;
+    b1[i] = i < g ? b[h + i] : 0u;
+  }
+  u64 sa = sub_vv<h>(da, a, a1);  // borrow <=> a0 < a1
+  sub_vv<h>(da2, a1, a);
+  select<h>(da, sa, da2, da);
+  u64 sb = sub_vv<h>(db, b, b1);
+  sub_vv<h>(db2, b1, b);
+  select<h>(db, sb, db2, db);
+  mul_ps<h, h>(p, da, db);
+  // mid = z0 + z2 -/+ p: a0 b1 + a1 b0 >= 0, at most 2h + 1 limbs
+  constexpr int W = 2 * h + 1;
+  u32 x0[W], x2[W], xp[W], m[W], mp[W], mm[W];
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    x0[i] = i < 2 * h ? z0[i] : 0u;
+    x2[i] = i < 2 * g ? z2[i] : 0u;
+    xp[i] = i < 2 * h ? p[i] : 0u;
+  }
+  add_vv<W>(m, x0, x2);
+  add_vv<W>(mp, m, xp);
+  sub_vv<W>(mm, m, xp);
+  select<W>(m, sa ^ sb, mp, mm);  // signs differ: the product of the differences is negative
+  // t = z0 + z2 B^(2h) + mid B^h; the true value fits 2L limbs
+  constexpr int T = 2 * L - h;
+  u32 lo[T], mx[T];
+#pragma unroll
+  for (int i = 0; i < 2 * h; i++) t[i] = z0[i];
+#pragma unroll
+  for (int i = 0; i < 2 * g; i++) t[2 * h + i] = z2[i];
+#pragma unroll
+  for (int i = 0; i < T; i++) {
+    lo[i] = t[h + i];
+    mx[i] = i < W ? m[i] : 0u;
+  }
+  add_vv<T>(t + h, lo, mx);
+}
+
 // r = a*b mod q by Barrett reduction (Eq. (barrett), Listing 4 generalised):
 //   a' = a*2^d, t = a'*b < qn^2, r1 = t >> (M-2), r2 = (r1*mu) >> (M+5),
 //   t - r2*qn in [0, 2qn) (one correction), result = (that mod qn) >> d.
 // The subtraction uses only the low L limbs, as in _dmulmod: the difference
 // fits in L limbs.  Products: L^2 (a*b) + L^2 (r1*mu) + L(L+1)/2 (r2*qn).
-template <int L>
+// KARA: the two full products by one level of Karatsuba (kara_mul).
+template <int L, bool KARA = false>
 __device__ __forceinline__ void barrett_mul(u32* r, const u32* a, const u32* b, const BarrettC<L>& c) {
   // a' = a << d (a < q so a' < qn < 2^(32L-4): no overflow past L limbs)
   u32 as[L];
@@ -395,9 +464,11 @@ __device__ __forceinline__ void barrett_mul(u32* r, const u32* a, const u32* b, 
 #pragma unroll
     for (int i = 1; i < L; i++) as[i] = __builtin_amdgcn_alignbit(a[i], a[i - 1], 32 - c.d);
   }
-  // t = a' * b, 2L limbs, product scanning
+  // t = a' * b, 2L limbs
   u32 t[2 * L];
-  {
+  if constexpr (KARA) {
+    kara_mul<L>(t, as, b);
+  } else {
     u64 acc = 0;
     u32 hi = 0;
 #pragma unroll
@@ -415,7 +486,11 @@ __device__ __forceinline__ void barrett_mul(u32* r, const u32* a, const u32* b, 
   for (int i = 0; i < L; i++) r1[i] = __builtin_amdgcn_alignbit(t[L + i], t[L - 1 + i], 26);
   // r2 = (r1 * mu) >> (M + 5) = >> (32L + 1): need product limbs L .. 2L-1 exactly
   u32 p[2 * L];
-  {
+  if constexpr (KARA) {
+    u32 muv[L];
+    to_vgprs<L>(muv, c.mu);
+    kara_mul<L>(p, r1, muv);
+  } else {
     u64 acc = 0;
     u32 hi = 0;
 #pragma unroll

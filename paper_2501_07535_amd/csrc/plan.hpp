@@ -38,6 +38,7 @@ struct NttPlan {
   NttConsts mul_consts;           // inverse after a fused pointwise product
   uint32_t* scratch = nullptr;    // for in-place multi-pass calls
   uint32_t* spectra = nullptr;    // 2 x n x L words: the two forward transforms of a cyclic product
+  uint32_t* stage = nullptr;      // n x L words: full-width moduli run through it (storage has L - 1 planes)
   NttSchedule sched;
   std::vector<NttPass> passes;
   std::mutex mu;  // guards scratch allocation and schedule changes
@@ -48,6 +49,7 @@ struct NttPlan {
     (void)hipFree(inv.ladder);
     (void)hipFree(scratch);
     (void)hipFree(spectra);
+    (void)hipFree(stage);
   }
 };
 

@@ -5,6 +5,9 @@
   python -m paper_2501_07535_amd.tuning evaluate --db DB.csv [DB2.csv ...] --out report.json --model cm.txt
       hold out shapes, train the model on the rest (on the GPU), and report the
       regret of timing only the model's top-k shapes against exhaustive search
+  python -m paper_2501_07535_amd.tuning widths --db DB.csv [...] --out widths.json
+      the autotuned transform time against the bit-width class at fixed sizes,
+      and the slowdown per doubling of the width (Section 5.4); no GPU needed
 
 Regret of a shape = t(fastest of the model's top-k) / t(fastest of all) - 1, with
 both times taken from the same exhaustive sweep.  The comparison baselines spend
@@ -125,6 +128,29 @@ def evaluate(paths, out, model_path, ks=(1, 3, 5, 10), holdout=0.2, seed=7, epoc
     return report
 
 
+def widths(paths, out, logns=(12, 16)):
+    """Autotuned (fastest measured) time per bit-width class at fixed n, and the
+    slowdown factor of each width doubling 64 -> 128 -> ... -> 1024."""
+    rows = load_rows(paths)
+    best = {}
+    for L, n, _, us in rows:
+        best[(L, n)] = min(us, best.get((L, n), float("inf")))
+    report = {"note": "class width = 32 x compute limbs (modulus of width - 4 bits)", "sizes": {}}
+    for logn in logns:
+        curve = {32 * L: round(us, 3) for (L, n), us in sorted(best.items()) if n == logn}
+        doublings = {}
+        w = 64
+        while 2 * w <= 1024:
+            if w in curve and 2 * w in curve:
+                doublings[f"{w}->{2 * w}"] = round(curve[2 * w] / curve[w], 3)
+            w *= 2
+        report["sizes"][str(logn)] = {"us_by_width": curve, "slowdown_per_doubling": doublings}
+    with open(out, "w") as fh:
+        json.dump(report, fh, indent=1)
+    print(json.dumps(report, indent=1), flush=True)
+    return report
+
+
 def default_schedule_time(moma, shp, cands):
     """Time of the schedule a fresh plan would pick by default for this shape, if it was measured."""
     from paper_2501_07535_amd import _default_schedule_for
@@ -149,8 +175,14 @@ def main():
     e.add_argument("--out", required=True)
     e.add_argument("--model", default=None)
     e.add_argument("--epochs", type=int, default=300)
+    w = sub.add_parser("widths")
+    w.add_argument("--db", nargs="+", required=True)
+    w.add_argument("--out", required=True)
+    w.add_argument("--logn", default="12,16")
     a = ap.parse_args()
-    if a.cmd == "collect":
+    if a.cmd == "widths":
+        widths(a.db, a.out, tuple(int(v) for v in a.logn.split(",")))
+    elif a.cmd == "collect":
         n = collect(a.db, _rng_range(a.widths), _rng_range(a.logn), a.reps, a.warmup)
         print(f"database rows: {n}", flush=True)
     else:

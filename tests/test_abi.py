@@ -72,9 +72,12 @@ def test_blas_rejects_bad_modulus(case):
         rc = lib.moma_vmul(_w(q + 1, L), L, 10, DUMMY, DUMMY, DUMMY, None)
         assert rc == moma.MOMA_E_MODULUS
     elif case == "q_too_wide":
-        wide = (1 << 253) + 1                      # 254 bits > 32*8-4
-        rc = lib.moma_vsub(_w(wide, L), L, 10, DUMMY, DUMMY, DUMMY, None)
-        assert rc == moma.MOMA_E_MODULUS
+        # a full-width 1024-bit modulus needs 33 internal limbs
+        wide = (1 << 1023) + 1
+        rc = lib.moma_vsub(_w(wide, 32), 32, 10, DUMMY, DUMMY, DUMMY, None)
+        assert rc == moma.MOMA_E_UNSUPPORTED
+        # full width below 1024 bits is accepted (n = 0: validation only)
+        assert lib.moma_vsub(_w((1 << 255) + 1, L), L, 0, None, None, None, None) == 0
     elif case == "q_null":
         rc = lib.moma_vadd(None, L, 10, DUMMY, DUMMY, DUMMY, None)
         assert rc == moma.MOMA_E_ARG
@@ -138,3 +141,23 @@ def test_cyclic_mul_rejects_null_buffers():
     q, w = _w(f.q, 8), _w(f.root(64), 8)
     for bufs in ((None, DUMMY, DUMMY), (DUMMY, None, DUMMY), (DUMMY, DUMMY, None)):
         assert lib.moma_ntt_cyclic_mul(q, w, 64, 8, *bufs, None) == moma.MOMA_E_ARG
+
+
+def test_vmul_variant_validation():
+    import moma_inputs as mi
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    f = mi.find_prime(256, 0)
+    assert lib.moma_vmul_set_variant(_w(f.q, 8), 8, 2) == moma.MOMA_E_ARG
+    assert lib.moma_vmul_get_variant(_w(f.q, 8), 8, None) == moma.MOMA_E_ARG
+    # a 27-bit modulus computes in one limb: no Karatsuba split
+    small = (1 << 27) - (1 << 12) + 1   # odd, 27 bits
+    assert lib.moma_vmul_set_variant(_w(small, 2), 2, 1) == moma.MOMA_E_UNSUPPORTED
+    assert moma.vmul_get_variant(f.q, 8) == moma.VMUL_SCHOOLBOOK
+    moma.vmul_set_variant(f.q, 8, moma.VMUL_KARATSUBA)
+    assert moma.vmul_get_variant(f.q, 8) == moma.VMUL_KARATSUBA
+    assert moma.vmul_get_variant(f.q, 9) == moma.VMUL_KARATSUBA     # same compute limb count
+    moma.vmul_set_variant(f.q, 8, moma.VMUL_SCHOOLBOOK)
+    buf = (ctypes.c_float * 2)()
+    assert lib.moma_vmul_tune(_w(f.q, 8), 8, 0, 3, buf, None) == moma.MOMA_E_ARG
+    assert lib.moma_vmul_tune(_w(f.q, 8), 8, 16, 3, None, None) == moma.MOMA_E_ARG

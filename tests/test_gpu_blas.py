@@ -96,3 +96,44 @@ def test_blas_full_size_sampled(lam, L):
     out = moma.axpy(alpha, da, db, q)
     got = mi.from_planar(out[:, torch.from_numpy(idx).to("cuda:0")].cpu().numpy().view(np.uint32))
     assert (got == oracle.axpy(q, L, alpha, a[idx], b[idx])).all()
+
+
+KARA_CASES = [(64, 2, 3000), (96, 3, 1025), (128, 4, 700), (160, 5, 513), (256, 8, 2049), (384, 12, 999),
+              (512, 16, 257), (768, 24, 300), (992, 31, 130), (1024, 32, 129)]
+
+
+@pytest.mark.parametrize("lam,L,n", KARA_CASES)
+def test_vmul_karatsuba_matches_oracle(lam, L, n):
+    """The Karatsuba product variant (even and odd limb counts) gives the oracle's
+    products, on random residues and on the edge vectors."""
+    import oracle
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(lam, 0)
+    q = f.q
+    a, b = mi.residues(f, n, L, 102, 1), mi.residues(f, n, L, 102, 2)
+    ev = mi.edge_vectors(f, n, L)
+    say(f"vmul karatsuba lam={lam} L={L} n={n}")
+    moma.vmul_set_variant(q, L, moma.VMUL_KARATSUBA)
+    try:
+        assert (from_dev(moma.vmul(to_dev(a), to_dev(b), q)) == oracle.vmul(q, L, a, b)).all()
+        names = list(ev)
+        for i, na in enumerate(names):
+            x, y = ev[na], ev[names[(i + 2) % len(names)]]
+            assert (from_dev(moma.vmul(to_dev(x), to_dev(y), q)) == oracle.vmul(q, L, x, y)).all(), na
+    finally:
+        moma.vmul_set_variant(q, L, moma.VMUL_SCHOOLBOOK)
+
+
+def test_vmul_tune_installs_a_variant():
+    import oracle
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(768, 0)
+    q, L = f.q, f.limbs
+    say("vmul tune 768")
+    r = moma.vmul_tune(q, L, 1 << 16, reps=3)
+    assert r["chosen"] in (moma.VMUL_SCHOOLBOOK, moma.VMUL_KARATSUBA)
+    assert r["schoolbook_us"] > 0 and r["karatsuba_us"] > 0
+    assert moma.vmul_get_variant(q, L) == r["chosen"]
+    a, b = mi.residues(f, 4097, L, 103, 1), mi.residues(f, 4097, L, 103, 2)
+    assert (from_dev(moma.vmul(to_dev(a), to_dev(b), q)) == oracle.vmul(q, L, a, b)).all()
+    moma.vmul_set_variant(q, L, moma.VMUL_SCHOOLBOOK)

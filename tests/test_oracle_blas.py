@@ -45,3 +45,18 @@ def test_blas_empty_vectors():
     z = np.zeros((0, 8), dtype=np.uint32)
     assert oracle.vadd(f.q, 8, z, z).shape == (0, 8)
     assert oracle.axpy(f.q, 8, 5, z, z).shape == (0, 8)
+
+
+@pytest.mark.parametrize("lam", [64, 256, 992])
+def test_full_width_modulus_matches_python_int(lam):
+    """A modulus as wide as its storage (bitlen(q) = 32 limbs): the oracle's
+    products and sums still equal Python's."""
+    import oracle
+    f = mi.find_prime(lam, 0, bits=lam)
+    q, L = f.q, f.limbs
+    assert q.bit_length() == 32 * L
+    a, b = mi.residues(f, 200, L, 8, 1), mi.residues(f, 200, L, 8, 2)
+    ai, bi = mi.rows_to_ints(a), mi.rows_to_ints(b)
+    assert mi.rows_to_ints(oracle.vadd(q, L, a, b)) == [(u + v) % q for u, v in zip(ai, bi)]
+    assert mi.rows_to_ints(oracle.vsub(q, L, a, b)) == [(u - v) % q for u, v in zip(ai, bi)]
+    assert mi.rows_to_ints(oracle.vmul(q, L, a, b)) == [(u * v) % q for u, v in zip(ai, bi)]

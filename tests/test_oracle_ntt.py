@@ -125,3 +125,13 @@ def test_root_order_is_exact():
         assert oracle.mod_pow(w, n // 2, f.q, 8) == f.q - 1
         if logn < 32:
             assert pow(f.root(2 * n), 2, f.q) == w
+
+
+@pytest.mark.parametrize("lam,logn", [(64, 5), (256, 4)])
+def test_full_width_modulus_direct_matches_pure_python(lam, logn):
+    import oracle
+    f = mi.find_prime(lam, 0, bits=lam)
+    n, L = 1 << logn, f.limbs
+    w = f.root(n)
+    x = mi.residues(f, n, L, 42, logn)
+    assert mi.rows_to_ints(oracle.ntt_radix2(f.q, L, w, x)) == py_ntt(mi.rows_to_ints(x), w, f.q)
