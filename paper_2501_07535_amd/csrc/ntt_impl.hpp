@@ -103,9 +103,28 @@ __device__ __forceinline__ u64 tw_pos(const TileGeo& t, u32 sg, u32 lb, u32 g) {
 // lies in block 0, so a pair whose local block index is 0 has twiddle
 // w^0 = 1 (table entry 2^s) and skips the multiply: all pairs of stage 0, half
 // of stage 1, a quarter of stage 2.
-template <int L, int R, bool FIRST>
-__device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, const u32* __restrict__ tw,
+// STORE: the pass's last round in a later pass (K > 0) with at least 16
+// columns (and at most 10 limbs): each unit writes its finished elements straight to their HBM
+// addresses (the rows of one column are consecutive across lanes, so every
+// store instruction covers 64-byte runs) instead of back to LDS, so the pass
+// has no separate store phase and the stores drain while other units compute.
+template <int L>
+__device__ __forceinline__ void finish_elem(u32* x, const NttPassArgs& a, const NttC<L>& c) {
+  if (a.last) {
+    u32 y[L];
+    if (a.scale) {
+      mont_mul_digits<L>(y, x, c.nscaled, c.qd, c.qinvd);  // x < 4q, scale < q: y in [0, 2q)
+    } else {
+      reduce_once<L>(y, x, c.q2);                           // [0, 4q) -> [0, 2q)
+    }
+    reduce_once<L>(x, y, c.q);                              // -> [0, q)
+  }
+}
+
+template <int L, int R, bool FIRST, bool STORE>
+__device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
                                           const NttC<L>& c) {
+  const u32* __restrict__ tw = a.tw;
   const u32 k = t.k;
   const u32 B = 1u << (k - sg0);        // block size (rows) at stage sg0
   const u32 sub = B >> R;                // row spacing of a unit's elements
@@ -138,10 +157,21 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
         }
       }
     }
+    if constexpr (STORE) {
+      const u64 base = (t.ro << (t.K + k)) + t.b0 + g;
 #pragma unroll
-    for (int e = 0; e < (1 << R); e++)
+      for (int e = 0; e < (1 << R); e++) {
+        const u64 dst = base + ((u64)rev_bits(p0 + e * sub, k) << t.K);
+        finish_elem<L>(x[e], a, c);
 #pragma unroll
-      for (int j = 0; j < L; j++) lds[(j * t.rows + p0 + e * sub) * t.C + g] = x[e][j];
+        for (int j = 0; j < L; j++) a.out[(u64)j * t.n + dst] = x[e][j];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < (1 << R); e++)
+#pragma unroll
+        for (int j = 0; j < L; j++) lds[(j * t.rows + p0 + e * sub) * t.C + g] = x[e][j];
+    }
   }
 }
 
@@ -149,13 +179,24 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
 // One tile of one pass: stages [K, K+k) on C = 2^logc groups of 2^k elements.
 // LDS holds the tile limb-planar: word (j * 2^k + u) * C + g is limb j of row u
 // of group g, so lanes with consecutive g touch consecutive banks.
+// the fused store keeps a unit's finished elements live while it stores them;
+// above 10 limbs that pushes the kernels into scratch memory
+template <int L>
+constexpr bool kFuseStore = L <= 10;
+
 template <int L, int R>
-__device__ __forceinline__ void round_at(u32* lds, const TileGeo& t, u32 sg0, const u32* __restrict__ tw,
-                                         const NttC<L>& c) {
+__device__ __forceinline__ void round_at(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
+                                         const NttC<L>& c, bool store) {
+  if constexpr (kFuseStore<L>) {
+    if (store) {
+      ntt_round<L, R, false, true>(lds, t, sg0, a, c);
+      return;
+    }
+  }
   if (t.K == 0 && sg0 == 0)
-    ntt_round<L, R, true>(lds, t, sg0, tw, c);
+    ntt_round<L, R, true, false>(lds, t, sg0, a, c);
   else
-    ntt_round<L, R, false>(lds, t, sg0, tw, c);
+    ntt_round<L, R, false, false>(lds, t, sg0, a, c);
 }
 
 // Fused pointwise product of a cyclic product's first inverse pass:
@@ -286,36 +327,29 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
   __syncthreads();
 
   // ---- stages, R at a time in registers
+  // later passes with 16+ columns store from the last round's registers
+  const bool fuse = kFuseStore<L> && t.K > 0 && t.C >= 16;
   u32 sg = 0;
   while (sg < t.k) {
     u32 rem = t.k - sg;
-    if (R >= 3 && rem >= 3) {
-      round_at<L, (R >= 3 ? 3 : 1)>(lds, t, sg, a.tw, c);
-      sg += (R >= 3 ? 3 : 1);
-    } else if (R >= 2 && rem >= 2) {
-      round_at<L, (R >= 2 ? 2 : 1)>(lds, t, sg, a.tw, c);
-      sg += (R >= 2 ? 2 : 1);
+    const u32 rr = (R >= 3 && rem >= 3) ? 3 : ((R >= 2 && rem >= 2) ? 2 : 1);
+    const bool store = fuse && sg + rr == t.k;
+    if (rr == 3) {
+      round_at<L, (R >= 3 ? 3 : 1)>(lds, t, sg, a, c, store);
+    } else if (rr == 2) {
+      round_at<L, (R >= 2 ? 2 : 1)>(lds, t, sg, a, c, store);
     } else {
-      round_at<L, 1>(lds, t, sg, a.tw, c);
-      sg += 1;
+      round_at<L, 1>(lds, t, sg, a, c, store);
     }
-    __syncthreads();
+    sg += rr;
+    if (!store) __syncthreads();
   }
+  if (fuse) return;
 
   // ---- store (canonical residues on the last pass), 4 words per lane per limb
   const u32 logn = a.logn;
-  auto finish = [&](u32* x) {
-    if (a.last) {
-      u32 y[L];
-      if (a.scale) {
-        mont_mul_digits<L>(y, x, c.nscaled, c.qd, c.qinvd);  // x < 4q, scale < q: y in [0, 2q)
-      } else {
-        reduce_once<L>(y, x, c.q2);                      // [0, 4q) -> [0, 2q)
-      }
-      reduce_once<L>(x, y, c.q);                         // -> [0, q)
-    }
-  };
-  constexpr bool kVecStore = L <= 16;  // 4 elements of L limbs stay in registers
+  auto finish = [&](u32* x) { finish_elem<L>(x, a, c); };
+  constexpr bool kVecStore = L <= 10;  // 4 elements of L limbs (and the scale multiply) stay in registers
   if (kVecStore && t.K > 0 && vec_g) {
     // same addresses as the load: 4 consecutive groups of one row
     for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
