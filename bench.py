@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line, print one JSON line per size of the transform sweep "
                          "(2^16..2^24 at 256 bits, 2^20 at 128/384/1024 bits)")
+    ap.add_argument("--forward-only", action="store_true",
+                    help="time only the headline forward transform (no default-schedule, inverse or cyclic-product "
+                         "timing): every transform kernel launched is a headline pass, for counter collection")
     ap.add_argument("--blas", action="store_true",
                     help="instead of the headline line, print one JSON line per modular BLAS op and width "
                          "(vadd/vsub/vmul/axpy at n=2^24, 256/384/768 bits)")
@@ -200,7 +203,7 @@ def main():
     moma.ntt_prepare(q, w, n, L)
     stream = torch.cuda.current_stream()
     default_sched = moma.ntt_get_schedule(q, w, n, L)
-    default_us = _time_fwd(moma, torch, stream, dx, dy, q, w, 3, 20)
+    default_us = None if args.forward_only else _time_fwd(moma, torch, stream, dx, dy, q, w, 3, 20)
     tuned = None
     if args.schedule:
         moma.ntt_set_schedule(q, w, n, L, tuple(int(v) for v in args.schedule.split(",")))
@@ -225,18 +228,20 @@ def main():
     ms_step = ms_total / args.steps
 
     # inverse transform timing (not the headline), same protocol
-    for _ in range(args.warmup):
-        moma.ntt_inv(dy, q, w, out=dz)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        moma.ntt_inv(dy, q, w, out=dz)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_inv = ev0.elapsed_time(ev1) / args.steps
+    ms_inv = None
+    if not args.forward_only:
+        for _ in range(args.warmup):
+            moma.ntt_inv(dy, q, w, out=dz)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            moma.ntt_inv(dy, q, w, out=dz)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_inv = ev0.elapsed_time(ev1) / args.steps
 
     # checks outside the timed region: round trip on the whole vector, and
     # sampled outputs against the oracle's definition
-    roundtrip = bool(torch.equal(dz, dx))
+    roundtrip = None if args.forward_only else bool(torch.equal(dz, dx))
     sampled_ok = None
     try:
         import oracle
@@ -246,7 +251,8 @@ def main():
     except Exception as e:  # the oracle is optional for the measurement itself
         print(f"oracle check skipped: {e}", file=sys.stderr)
 
-    cyc = cyclic_product(moma, torch, stream, dx, dy, dz, q, w, n, args.warmup, args.steps)
+    cyc = None if args.forward_only else cyclic_product(moma, torch, stream, dx, dy, dz, q, w, n, args.warmup,
+                                                         args.steps)
 
     B = n // 2 * logn
     gbfly = B / (ms_step * 1e-3) / 1e9
@@ -294,14 +300,15 @@ def main():
                    "layout": "limb-planar", "twiddles": "precomputed table"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "Tops/s",
                      "frac": round(achieved / peak, 4),
-                     "traffic": measured_traffic(lam, logn, moma.ntt_get_schedule(q, w, n, L)),
+                     "traffic": measured_traffic(lam, logn, moma.ntt_get_schedule(q, w, n, L), plan["stages"]),
                      "kernel": f"ntt_pass_kernel<{L}>", "launches_per_step": launches,
                      "avg_launch_us": round(launch_ms * 1e3, 3),
                      "ops_per_butterfly": alg_ops_per_butterfly(L), "pass_stages": plan["stages"],
                      "schedule": list(moma.ntt_get_schedule(q, w, n, L))},
         "cpu_baseline": cpu,
-        "extras": {"fwd_us": round(ms_step * 1e3, 3), "inv_us": round(ms_inv * 1e3, 3),
-                   "default_schedule": list(default_sched), "default_schedule_fwd_us": round(default_us, 3),
+        "extras": {"fwd_us": round(ms_step * 1e3, 3), "inv_us": round(ms_inv * 1e3, 3) if ms_inv else None,
+                   "default_schedule": list(default_sched),
+                   "default_schedule_fwd_us": round(default_us, 3) if default_us else None,
                    "autotuned": tuned,
                    "ns_per_butterfly_paper_metric": round(2 * ms_step * 1e6 / (n * logn), 6),
                    "hbm_bytes_min_per_step": 2 * n * 4 * L,
@@ -314,9 +321,11 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def measured_traffic(lam, logn, schedule):
+def measured_traffic(lam, logn, schedule, stages):
     """HBM bytes per pass-kernel launch from the committed rocprofv3 counters, if
-    they were taken on the current kernel sources with this launch shape."""
+    they were taken on the current kernel sources with the same launches (pass
+    stages, columns per tile, threads and register radix; the tile size bound
+    itself does not change the launches)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"ntt_traffic_L{(lam + 31) // 32}_{lam}bit_n2e{logn}.json")
     if not os.path.exists(path):
@@ -325,7 +334,8 @@ def measured_traffic(lam, logn, schedule):
     h = hashlib.sha256()
     for f in rec["sources"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != rec["kernel_sources_sha256"] or list(rec["schedule"]) != list(schedule):
+    same = (list(rec["pass_stages"]) == list(stages) and list(rec["schedule"])[1:] == list(schedule)[1:])
+    if h.hexdigest() != rec["kernel_sources_sha256"] or not same:
         return None
     return rec["traffic_bytes_per_launch"]
 
