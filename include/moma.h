@@ -106,8 +106,8 @@ int moma_axpy(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* alp
  *   moma_vmul_set_variant / moma_vmul_get_variant: the variant used by later
  *     moma_vmul calls whose modulus has the same compute limb count
  *     (MOMA_E_UNSUPPORTED for Karatsuba below 2 compute limbs);
- *   moma_vmul_tune: times each variant on n zero residues (median of reps
- *     runs after one warm-up; reps 0 means 5), installs the faster, writes the
+ *   moma_vmul_tune: times each variant on n pseudo-random residues (median
+ *     of reps runs after one warm-up; reps 0 means 5), installs the faster, writes the
  *     two times in microseconds to us_out[2] (us_out[1] = 0 when only
  *     schoolbook applies) and the choice to *chosen (may be NULL).  Allocates
  *     3 n L words for the duration of the call and synchronises.
@@ -203,8 +203,10 @@ int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, 
  * append every measurement to the process's timing database.  With top_k > 0
  * and a cost model loaded, only the model's top_k shapes are timed (without a
  * model that returns MOMA_E_UNSUPPORTED).  max_candidates > 0 truncates the
- * enumeration.  Ties go to the earlier candidate.  Allocates two scratch
- * transforms and synchronises.
+ * enumeration.  Ties go to the earlier candidate.  The timed input is n
+ * pseudo-random residues (the clock under load depends on the data, so zeros
+ * would time optimistically).  Allocates two scratch transforms and
+ * synchronises.
  */
 typedef struct moma_tune_opts {
   uint32_t reps;            /* timed repetitions per shape (median), default 5 */

@@ -113,6 +113,32 @@ int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, 
 
 namespace moma {
 
+// Timing inputs: word i of plane j is a hash of (i, seed); planes below the
+// top limb of q are uniform, the top limb is masked below q's top limb, the
+// planes above it are zero, so every element is a residue below q.
+__global__ __launch_bounds__(256) void fill_residues_kernel(u32* __restrict__ p, u64 n, int planes, int top,
+                                                            u32 top_mask, u32 seed) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * (u64)planes) return;
+  int j = (int)(i / n);
+  u32 x = (u32)i ^ (u32)(i >> 32) * 0x9e3779b9u ^ seed;
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  p[i] = j < top ? x : (j == top ? (x & top_mask) : 0u);
+}
+
+int launch_fill_residues(uint32_t* p, uint64_t n, int planes, int top, uint32_t top_mask, uint32_t seed,
+                         hipStream_t s) {
+  u64 count = n * (u64)planes;
+  if (count == 0) return 0;
+  hipLaunchKernelGGL(fill_residues_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, n, planes, top,
+                     top_mask, seed);
+  return (int)hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void copy_words_kernel(u32* __restrict__ dst, const u32* __restrict__ src, u64 count) {
   u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) dst[i] = src[i];

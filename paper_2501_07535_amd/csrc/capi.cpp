@@ -329,6 +329,18 @@ static int enqueue_passes(NttPlan& p, const std::vector<NttPass>& passes, const 
   return MOMA_OK;
 }
 
+int fill_random_residues(const FieldRaw& f, uint32_t* d, uint64_t n, uint32_t seed, hipStream_t s) {
+  int top = kMaxLimbs - 1;
+  while (top > 0 && f.q[top] == 0) top--;
+  uint32_t m = f.q[top];  // q's top limb, >= 1: keep the top word strictly below it
+  uint32_t mask = 0;
+  while (mask < (m >> 1)) mask = (mask << 1) | 1u;
+  if (mask >= m) mask >>= 1;
+  int e = launch_fill_residues(d, n, f.Ls, top, mask, seed, s);
+  if (!e) e = (int)hipStreamSynchronize(s);
+  return e ? hip_fail(e, "random residues") : MOMA_OK;
+}
+
 // lazily allocated per-plan buffer of n x L words (under the plan's mutex)
 static int plan_buffer(NttPlan& p, uint32_t** slot, size_t copies, const char* what) {
   if (!*slot && hipMalloc((void**)slot, copies * (size_t)p.n * p.fe->f.L * sizeof(uint32_t)))
@@ -567,13 +579,16 @@ int moma_vmul_tune(const uint32_t* q, uint32_t limbs, uint64_t n, uint32_t reps,
   if (reps == 0) reps = 5;
   const int L = fe->f.L;
   const uint32_t nvar = L >= 2 ? 2 : 1;
-  // zero residues: the kernels' timing does not depend on the values
+  // random residues in the caller's storage planes: the kernels' power draw,
+  // and with it the clock, depends on the data
+  const int planes = std::max(L, fe->f.Ls);
   uint32_t* buf = nullptr;
-  const size_t words = (size_t)n * L;
+  const size_t words = (size_t)n * planes;
   if (hipMalloc((void**)&buf, 3 * words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, "tune buffers");
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  int err = (int)hipMemset(buf, 0, 3 * words * sizeof(uint32_t));
+  int err = fill_random_residues(fe->f, buf, n, 0x5eed2u, nullptr);
+  if (!err) err = fill_random_residues(fe->f, buf + words, n, 0x5eed3u, nullptr);
   if (!err) err = (int)hipStreamCreate(&st);
   if (!err) err = (int)hipEventCreate(&e0);
   if (!err) err = (int)hipEventCreate(&e1);
@@ -586,6 +601,7 @@ int moma_vmul_tune(const uint32_t* q, uint32_t limbs, uint64_t n, uint32_t reps,
     a.b = buf + words;
     a.out = buf + 2 * words;
     a.n = n;
+    a.ls = (uint32_t)fe->f.Ls;
     a.variant = v;
     std::vector<float> t;
     for (uint32_t r = 0; r < reps + 1 && !err; r++) {

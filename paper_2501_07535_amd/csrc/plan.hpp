@@ -64,6 +64,9 @@ int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>
 NttSchedule default_schedule(int L, uint32_t logn);
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s);
 int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s);
+// n pseudo-random residues below q in Ls = f.Ls storage planes (timing inputs for the tuners)
+int fill_random_residues(const FieldRaw& f, uint32_t* d, uint64_t n, uint32_t seed, hipStream_t s);
+int launch_fill_residues(uint32_t* p, uint64_t n, int planes, int top, uint32_t top_mask, uint32_t seed, hipStream_t s);
 // tuner (tune.cpp)
 std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn);
 bool tune_db_best(const std::string& dev, int L, uint32_t logn, NttSchedule* out);

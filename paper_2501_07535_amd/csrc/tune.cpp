@@ -161,13 +161,21 @@ static int tune(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t l
   }
   if (opts.max_candidates > 0 && cands.size() > opts.max_candidates) cands.resize(opts.max_candidates);
   if (cands.empty()) return set_error(MOMA_E_UNSUPPORTED, "no feasible schedule");
-  size_t words = (size_t)p->n * L;
+  // the caller's storage planes (a transform writes all of them), at least the compute limbs
+  const int planes = std::max(L, p->fe->f.Ls);
+  size_t words = (size_t)p->n * planes;
   uint32_t *din = nullptr, *dout = nullptr;
   if (hipMalloc((void**)&din, words * 4) || hipMalloc((void**)&dout, words * 4)) {
     (void)hipFree(din);
     return set_error(MOMA_E_NOMEM, "tuner buffers");
   }
-  (void)hipMemset(din, 0, words * 4);
+  // random residues: the kernels' power draw, and with it the clock, depends on the data
+  rc = fill_random_residues(p->fe->f, din, p->n, 0x5eed1u, nullptr);
+  if (rc) {
+    (void)hipFree(din);
+    (void)hipFree(dout);
+    return rc;
+  }
   hipStream_t st;
   hipEvent_t e0, e1;
   (void)hipStreamCreate(&st);

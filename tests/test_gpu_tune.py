@@ -62,3 +62,25 @@ def test_costmodel_ranks_and_top_k(tmp_path):
     moma.costmodel_clear()
     with pytest.raises(moma.MomaError):
         moma.ntt_tune(f.q, f.root(1 << 12), 1 << 12, f.limbs, top_k=3)
+
+
+def test_tuners_with_storage_wider_than_the_modulus():
+    """The tuners' own buffers hold the caller's storage planes (a transform
+    zero-fills the planes above the compute limbs), here 10 planes for a
+    252-bit modulus; the tuned plan still gives the oracle's transform."""
+    import oracle
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(256, 0)
+    q, n, Ls = f.q, 1 << 12, 10
+    w = f.root(n)
+    say("tune wide storage")
+    r = moma.ntt_tune(q, w, n, Ls, reps=1, warmup=1, max_candidates=6)
+    assert r["timed"] >= 1 and r["best_us"] > 0
+    x = mi.residues(f, n, Ls, 600)
+    assert (from_dev(moma.ntt_fwd(to_dev(x), q, w)) == oracle.ntt_radix2(q, Ls, w, x)).all()
+    v = moma.vmul_tune(q, Ls, 4096, reps=2)
+    assert v["schoolbook_us"] > 0 and v["karatsuba_us"] > 0
+    a, b = mi.residues(f, 999, Ls, 601, 1), mi.residues(f, 999, Ls, 601, 2)
+    assert (from_dev(moma.vmul(to_dev(a), to_dev(b), q)) == oracle.vmul(q, Ls, a, b)).all()
+    moma.vmul_set_variant(q, Ls, moma.VMUL_SCHOOLBOOK)
+    moma.ntt_set_schedule(q, w, n, Ls, None)
