@@ -185,11 +185,16 @@ typedef struct moma_ntt_schedule {
 } moma_ntt_schedule_t;
 
 /* Set the schedule of the plan for (q, omega, n, limbs); NULL restores the
- * default.  MOMA_E_UNSUPPORTED if the shape cannot run this size, MOMA_E_ARG
- * for malformed values.  Affects calls enqueued afterwards. */
+ * plan's initial choice: the timing database's fastest schedule for this
+ * (compute limbs, n) if it has one, else the loaded cost model's top-ranked
+ * schedule, else the fixed rule of moma_ntt_default_schedule.  New plans
+ * start with that same choice.  MOMA_E_UNSUPPORTED if the shape cannot run
+ * this size, MOMA_E_ARG for malformed values.  Affects calls enqueued
+ * afterwards. */
 int moma_ntt_set_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
                           const moma_ntt_schedule_t* sched);
-/* The schedule a new plan uses when the timing database has no entry for it. */
+/* The fixed rule a new plan falls back to when neither the timing database
+ * nor a loaded cost model gives it a schedule. */
 int moma_ntt_default_schedule(uint32_t limbs_compute, uint32_t log2_n, moma_ntt_schedule_t* sched);
 /* Read the schedule the plan currently uses. */
 int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
@@ -252,7 +257,10 @@ int moma_tune_db_load(const char* path);
  * log2 n, compute limbs, log2 radix, stages fused per pass, log2 threads,
  * log2 LDS bytes), trained on the GPU by the library's own kernels with Adam
  * on mean squared error.  Features and targets are z-scored with the training
- * set's statistics, which are saved with the weights.
+ * set's statistics, which are saved with the weights.  While a model is
+ * loaded (or trained), new plans whose shape the timing database does not
+ * cover start from the model's top-ranked schedule (one prediction per
+ * (compute limbs, log2 n), cached until the model changes).
  */
 typedef struct moma_train_opts {
   uint32_t epochs;          /* default 200 */

@@ -339,7 +339,7 @@ def _default_schedule_for(limbs_compute: int, log2_n: int) -> tuple:
 
 
 def ntt_default_schedule(limbs_compute: int, log2_n: int) -> tuple:
-    """The schedule a fresh plan uses without a tuning database entry."""
+    """The fixed rule a fresh plan falls back to without timings or a loaded cost model."""
     return _default_schedule_for(limbs_compute, log2_n)
 
 
@@ -509,3 +509,20 @@ def mlp_adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, e
 
 def shutdown():
     _lib.moma_shutdown()
+
+
+# The cost model trained on this device class's timing database (written by
+# `python -m paper_2501_07535_amd.tuning evaluate --model ...`): loaded at
+# import so that new plans without timings start from its top-ranked
+# schedule.  MOMA_NO_COSTMODEL=1 keeps the fixed default rule instead.
+COSTMODEL_PATH = os.path.join(_HERE, "costmodel_gfx950.txt")
+
+
+def load_packaged_costmodel() -> bool:
+    if os.path.exists(COSTMODEL_PATH) and not os.environ.get("MOMA_NO_COSTMODEL"):
+        costmodel_load(COSTMODEL_PATH)
+        return True
+    return False
+
+
+load_packaged_costmodel()

@@ -9,7 +9,8 @@
 // kernels are compiled per limb count) and by their plans' register radix and
 // workgroup size, and each group becomes one launch of
 // ntt_batch_kernel over a flat list of (pass record, tile) items, sorted by
-// decreasing work and dealt round-robin to a fixed grid.  Phases follow one
+// decreasing work, one workgroup per item (the dispatcher starts the largest
+// tiles first).  Phases follow one
 // another in stream order, which is the only dependency between a job's
 // passes.  The launches are captured once into a graph; running the batch is
 // one hipGraphLaunch.
@@ -236,7 +237,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       bl.threads = std::get<2>(kv.first);
       bl.lds = kv.second.lds[ph];
       bl.nitems = (uint32_t)items.size();
-      bl.grid = std::min<uint32_t>(bl.nitems, 4096);
+      bl.grid = bl.nitems;  // one workgroup per item
       bl.d_passes = (const NttPassArgs*)dev_recs[kv.first].first;
       bl.d_consts = dev_recs[kv.first].second;
       bl.d_items = (const uint2*)di;

@@ -185,6 +185,17 @@ NttSchedule default_schedule(int L, uint32_t logn) {
   return cands.back();
 }
 
+NttSchedule initial_schedule(int L, uint32_t logn) {
+  std::string keep = g_detail;
+  NttSchedule s;
+  std::vector<NttPass> ps;
+  bool ok = tune_db_best(current_device_name(), L, logn, &s) && plan_passes(L, logn, s, &ps) == MOMA_OK;
+  if (!ok) ok = costmodel_pick(L, logn, &s) && plan_passes(L, logn, s, &ps) == MOMA_OK;
+  if (!ok) s = default_schedule(L, logn);
+  g_detail = keep;
+  return s;
+}
+
 static int check_planes(const NttPlan& p) {
   for (const NttPass& s : p.passes) {
     if (s.K == 0 && (p.n >> s.k) < (1ull << s.logc)) return -1;
@@ -260,14 +271,7 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   p->n = n;
   p->logn = 0;
   while ((1ull << p->logn) < n) p->logn++;
-  p->sched = default_schedule(fe->f.L, p->logn);
-  NttSchedule tuned;
-  std::vector<NttPass> tuned_passes;
-  std::string keep = g_detail;
-  if (tune_db_best(current_device_name(), fe->f.L, p->logn, &tuned) &&
-      plan_passes(fe->f.L, p->logn, tuned, &tuned_passes) == MOMA_OK)
-    p->sched = tuned;
-  g_detail = keep;
+  p->sched = initial_schedule(fe->f.L, p->logn);
   rc = plan_passes(fe->f.L, p->logn, p->sched, &p->passes);
   if (rc) return rc;
   if (check_planes(*p)) return set_error(MOMA_E_UNSUPPORTED, "no valid pass split for this size");
@@ -683,7 +687,7 @@ int moma_ntt_set_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, 
   int rc = get_plan(q, omega, n, limbs, &p);
   if (rc) return rc;
   NttSchedule s = sched ? NttSchedule{sched->tile_log, sched->col_log, sched->threads, sched->radix_log}
-                        : default_schedule(p->fe->f.L, p->logn);
+                        : initial_schedule(p->fe->f.L, p->logn);
   std::vector<NttPass> ps;
   rc = plan_passes(p->fe->f.L, p->logn, s, &ps);
   if (rc) return rc;

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -48,6 +49,10 @@ struct CostModel {
 
 static std::mutex g_cm_mu;
 static CostModel g_cm;
+static uint64_t g_cm_gen = 0;  // bumped whenever the model changes
+// the model's pick per (compute limbs, log2 n), valid for model generation g_pick_gen
+static std::map<std::pair<int, uint32_t>, NttSchedule> g_pick;
+static uint64_t g_pick_gen = 0;
 
 static uint64_t sm64(uint64_t key, uint64_t i) {
   uint64_t z = key + (i + 1) * 0x9E3779B97F4A7C15ull;
@@ -104,6 +109,37 @@ int costmodel_scores(int L, uint32_t logn, const std::vector<NttSchedule>& cands
   scores->assign(cands.size(), 0.f);
   std::lock_guard<std::mutex> lk(g_cm_mu);
   return predict_locked(f.data(), (uint32_t)cands.size(), scores->data());
+}
+
+bool costmodel_pick(int L, uint32_t logn, NttSchedule* out) {
+  const std::pair<int, uint32_t> key(L, logn);
+  {
+    std::lock_guard<std::mutex> lk(g_cm_mu);
+    if (!g_cm.ready) return false;
+    if (g_pick_gen != g_cm_gen) {
+      g_pick.clear();
+      g_pick_gen = g_cm_gen;
+    }
+    auto it = g_pick.find(key);
+    if (it != g_pick.end()) {
+      *out = it->second;
+      return true;
+    }
+  }
+  std::string keep = g_detail;
+  std::vector<NttSchedule> cands = enumerate_schedules(L, logn);
+  std::vector<float> sc;
+  if (cands.empty() || costmodel_scores(L, logn, cands, &sc) != MOMA_OK) {
+    g_detail = keep;
+    return false;
+  }
+  size_t best = 0;
+  for (size_t i = 1; i < cands.size(); i++)
+    if (sc[i] < sc[best]) best = i;
+  *out = cands[best];
+  std::lock_guard<std::mutex> lk(g_cm_mu);
+  g_pick[key] = *out;
+  return true;
 }
 
 static void he_init(uint64_t seed, std::vector<float>* p) {
@@ -285,12 +321,14 @@ int moma_costmodel_load(const char* path) {
   m.ready = true;
   std::lock_guard<std::mutex> lk(g_cm_mu);
   g_cm = m;
+  g_cm_gen++;
   return MOMA_OK;
 }
 
 void moma_costmodel_clear(void) {
   std::lock_guard<std::mutex> lk(g_cm_mu);
   g_cm = CostModel();
+  g_cm_gen++;
 }
 
 }  // extern "C"

@@ -432,19 +432,19 @@ __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kern
 
 // One phase of a batch: items[i] = (pass record, tile); every pass record names
 // its own transform (buffers, size, stages, twiddles) and its modulus constants.
-// Items are sorted by decreasing cost and dealt round-robin to a fixed grid.
+// Workgroup i runs item i; items are sorted by decreasing cost, so the
+// dispatcher hands out the largest tiles first.
 template <int L, int R, bool MUL>
 __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_kernel(
     const NttPassArgs* __restrict__ passes, const NttC<L>* __restrict__ consts, const uint2* __restrict__ items,
     u32 nitems) {
   extern __shared__ u32 lds[];
-  for (u32 i = blockIdx.x; i < nitems; i += gridDim.x) {
-    uint2 it = items[i];
-    const NttPassArgs a = passes[it.x];
-    const NttC<L> c = consts[it.x];
-    pass_tile<L, R, MUL>(lds, a, c, it.y);
-    __syncthreads();
-  }
+  const u32 i = blockIdx.x;
+  if (i >= nitems) return;
+  const uint2 it = items[i];
+  const NttPassArgs a = passes[it.x];
+  const NttC<L> c = consts[it.x];
+  pass_tile<L, R, MUL>(lds, a, c, it.y);
 }
 
 // Twiddle table: entry e = 2^s + i' holds w^(i' * 2^(logn-s-1)) * 2^(32L) mod q.

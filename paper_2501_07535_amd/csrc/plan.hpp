@@ -73,5 +73,11 @@ bool tune_db_best(const std::string& dev, int L, uint32_t logn, NttSchedule* out
 std::string current_device_name();
 // cost model (costmodel.cpp): predicted log-time per schedule; MOMA_E_UNSUPPORTED without a model
 int costmodel_scores(int L, uint32_t logn, const std::vector<NttSchedule>& cands, std::vector<float>* scores);
+// the loaded model's fastest predicted schedule for (L, log2 n), cached per
+// shape until the model changes; false when no model is loaded
+bool costmodel_pick(int L, uint32_t logn, NttSchedule* out);
+// a new plan's schedule: the timing database's best, else the cost model's
+// pick, else the fixed rule of default_schedule
+NttSchedule initial_schedule(int L, uint32_t logn);
 
 }  // namespace moma

@@ -5,6 +5,9 @@
   python -m paper_2501_07535_amd.tuning evaluate --db DB.csv [DB2.csv ...] --out report.json --model cm.txt
       hold out shapes, train the model on the rest (on the GPU), and report the
       regret of timing only the model's top-k shapes against exhaustive search
+  python -m paper_2501_07535_amd.tuning train --db DB.csv [...] --model cm.txt
+      train the cost model on every shape (the model a package ships: new plans
+      without timings start from its top-ranked schedule)
   python -m paper_2501_07535_amd.tuning widths --db DB.csv [...] --out widths.json
       the autotuned transform time against the bit-width class at fixed sizes,
       and the slowdown per doubling of the width (Section 5.4); no GPU needed
@@ -128,6 +131,18 @@ def evaluate(paths, out, model_path, ks=(1, 3, 5, 10), holdout=0.2, seed=7, epoc
     return report
 
 
+def train_all(paths, model_path, seed=7, epochs=300, batch=256, lr=3e-3):
+    import paper_2501_07535_amd as moma
+    rows = load_rows(paths)
+    feats = np.array([moma.costmodel_features(L, n, s) for L, n, s, _ in rows], np.float32)
+    y = np.log(np.array([us for *_, us in rows], np.float32))
+    t0 = time.time()
+    mse = moma.costmodel_train(feats, y, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    moma.costmodel_save(model_path)
+    print(json.dumps({"rows": len(rows), "train_mse_log_us": mse, "train_seconds": round(time.time() - t0, 2),
+                      "model": model_path}), flush=True)
+
+
 def widths(paths, out, logns=(12, 16)):
     """Autotuned (fastest measured) time per bit-width class at fixed n, and the
     slowdown factor of each width doubling 64 -> 128 -> ... -> 1024."""
@@ -175,12 +190,18 @@ def main():
     e.add_argument("--out", required=True)
     e.add_argument("--model", default=None)
     e.add_argument("--epochs", type=int, default=300)
+    t = sub.add_parser("train")
+    t.add_argument("--db", nargs="+", required=True)
+    t.add_argument("--model", required=True)
+    t.add_argument("--epochs", type=int, default=300)
     w = sub.add_parser("widths")
     w.add_argument("--db", nargs="+", required=True)
     w.add_argument("--out", required=True)
     w.add_argument("--logn", default="12,16")
     a = ap.parse_args()
-    if a.cmd == "widths":
+    if a.cmd == "train":
+        train_all(a.db, a.model, epochs=a.epochs)
+    elif a.cmd == "widths":
         widths(a.db, a.out, tuple(int(v) for v in a.logn.split(",")))
     elif a.cmd == "collect":
         n = collect(a.db, _rng_range(a.widths), _rng_range(a.logn), a.reps, a.warmup)

@@ -137,3 +137,30 @@ def test_vmul_tune_installs_a_variant():
     a, b = mi.residues(f, 4097, L, 103, 1), mi.residues(f, 4097, L, 103, 2)
     assert (from_dev(moma.vmul(to_dev(a), to_dev(b), q)) == oracle.vmul(q, L, a, b)).all()
     moma.vmul_set_variant(q, L, moma.VMUL_SCHOOLBOOK)
+
+
+@pytest.mark.parametrize("lam,n", [(256, 4096), (384, 2048), (128, 1024)])
+def test_blas_unaligned_buffers(lam, n):
+    """Planes that are not 16-byte aligned (a buffer starting one word into an
+    allocation) take the one-element-per-lane kernels; results are unchanged."""
+    import oracle
+    import torch
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(lam, 0)
+    q, L = f.q, f.limbs
+    a, b = mi.residues(f, n, L, 104, 1), mi.residues(f, n, L, 104, 2)
+
+    def shifted(x):
+        flat = torch.empty(L * n + 1, dtype=torch.int32, device="cuda:0")
+        v = flat[1:].view(L, n)
+        v.copy_(to_dev(x))
+        return v
+
+    da, db = shifted(a), shifted(b)
+    out = torch.empty(L * n + 1, dtype=torch.int32, device="cuda:0")[1:].view(L, n)
+    say(f"blas unaligned lam={lam} n={n}")
+    for op in ("vadd", "vsub", "vmul"):
+        getattr(moma, op)(da, db, q, out=out)
+        assert (from_dev(out) == getattr(oracle, op)(q, L, a, b)).all(), op
+    moma.axpy(7, da, db, q, out=out)
+    assert (from_dev(out) == oracle.axpy(q, L, 7, a, b)).all()

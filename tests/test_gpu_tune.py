@@ -62,6 +62,32 @@ def test_costmodel_ranks_and_top_k(tmp_path):
     moma.costmodel_clear()
     with pytest.raises(moma.MomaError):
         moma.ntt_tune(f.q, f.root(1 << 12), 1 << 12, f.limbs, top_k=3)
+    moma.load_packaged_costmodel()
+
+
+def test_new_plans_take_the_models_pick():
+    """With the packaged model loaded and no timings for a shape, a new plan
+    starts from the candidate with the lowest predicted time; the transform is
+    still the oracle's."""
+    import oracle
+    import paper_2501_07535_amd as moma
+    if not moma.load_packaged_costmodel():
+        pytest.skip("no packaged cost model")
+    moma.tune_db_clear()
+    moma.shutdown()
+    f = mi.find_prime(384, 7)
+    L, logn = f.limbs, 15
+    n, w = 1 << logn, f.root(1 << logn)
+    cands = moma.ntt_candidates(L, logn)
+    feats = np.array([moma.costmodel_features(L, logn, s) for s in cands], np.float32)
+    pick = tuple(cands[int(np.argmin(moma.costmodel_predict(feats)))])
+    say(f"model pick 384-bit 2^{logn}: {pick}")
+    assert moma.ntt_get_schedule(f.q, w, n, L) == pick
+    x = mi.residues(f, n, L, 602)
+    assert (from_dev(moma.ntt_fwd(to_dev(x), f.q, w)) == oracle.ntt_radix2(f.q, L, w, x)).all()
+    moma.ntt_set_schedule(f.q, w, n, L, moma.ntt_default_schedule(L, logn))
+    moma.ntt_set_schedule(f.q, w, n, L, None)                 # back to the model's pick
+    assert moma.ntt_get_schedule(f.q, w, n, L) == pick
 
 
 def test_tuners_with_storage_wider_than_the_modulus():
