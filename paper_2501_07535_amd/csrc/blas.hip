@@ -99,11 +99,12 @@ __global__ __launch_bounds__(256) void blas_kernel(const u32* __restrict__ pa, c
   }
 }
 
-// elements per lane: 4 up to 8 limbs; 2 for the add-class ops up to 16 limbs
-// (the multiply's temporaries leave no room for a second element there)
+// elements per lane.  4 (16-byte accesses) was measured at n = 2^24: vadd at
+// 256 bits took 333 us against 280 us with one element per lane, so every op
+// runs one element per lane; the vector path stays for experiments.
 template <int L, int OP>
 constexpr int blas_vec() {
-  return L <= 8 ? 4 : ((L <= 16 && (OP == OP_VADD || OP == OP_VSUB)) ? 2 : 1);
+  return 1;
 }
 
 template <int L, int OP, bool KARA, int V>
