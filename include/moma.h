@@ -296,29 +296,45 @@ int moma_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, 
                   float beta2, float eps, void* stream);
 
 /*
- * Batched transforms (the paper batches kernels to fill the GPU, Section 5.1):
- * many NTTs of different sizes, limb counts and moduli run as one hipGraph
- * launch.  A job is one call of the kind moma_ntt_fwd, moma_ntt_inv or
- * moma_ntt_cyclic_mul runs, with the same argument meanings and
- * preconditions; its plan is built (and shared with identical jobs) by
- * moma_batch_create, and a cyclic product gets 2 * n * L words of spectra
+ * Batched transforms and BLAS calls (the paper batches kernels to fill the
+ * GPU, Section 5.1): many NTTs and vector operations of different sizes,
+ * limb counts and moduli run as one hipGraph launch.  A job is one call of
+ * the kind moma_ntt_fwd, moma_ntt_inv, moma_ntt_cyclic_mul, moma_vadd,
+ * moma_vsub, moma_vmul or moma_axpy runs, with the same argument meanings and
+ * preconditions; transform plans are built (and shared with identical jobs)
+ * by moma_batch_create, and a cyclic product gets 2 * n * L words of spectra
  * scratch of its own, owned by the batch.  The batch keeps the job buffers'
  * addresses: they must stay allocated, and are read and written by every
  * moma_batch_run.  Each job's output equals what the plain call with the same
  * arguments produces, bit for bit.  Jobs must not overlap one another's
  * output buffers, and no job may read another job's output.
+ * Field use by kind:
+ *   transforms: omega, n (a power of two), d_in (cyclic product: a), d_in2
+ *     (cyclic product: b), d_out;
+ *   BLAS: n (any, 0 is a no-op), d_in = a (axpy: x), d_in2 = b (axpy: y),
+ *     d_out, and for axpy the host scalar alpha; omega is ignored.  vmul
+ *     uses the product variant set for its compute limb count at creation.
  */
-enum moma_job_kind { MOMA_JOB_FORWARD = 0, MOMA_JOB_INVERSE = 1, MOMA_JOB_CYCLIC_MUL = 2 };
+enum moma_job_kind {
+  MOMA_JOB_FORWARD = 0,
+  MOMA_JOB_INVERSE = 1,
+  MOMA_JOB_CYCLIC_MUL = 2,
+  MOMA_JOB_VADD = 3,
+  MOMA_JOB_VSUB = 4,
+  MOMA_JOB_VMUL = 5,
+  MOMA_JOB_AXPY = 6
+};
 
 typedef struct moma_ntt_job {
   const uint32_t* q;      /* host, limbs words */
-  const uint32_t* omega;  /* host, limbs words: forward primitive n-th root */
+  const uint32_t* omega;  /* host, limbs words: forward primitive n-th root (transforms) */
   uint64_t n;
   uint32_t limbs;
   uint32_t kind;          /* enum moma_job_kind */
-  const uint32_t* d_in;   /* device, limb-planar (cyclic product: a) */
+  const uint32_t* d_in;   /* device, limb-planar (cyclic product: a; BLAS: a or x) */
   uint32_t* d_out;        /* device, limb-planar; may equal d_in (or d_in2) */
-  const uint32_t* d_in2;  /* device, limb-planar: b of a cyclic product; ignored otherwise */
+  const uint32_t* d_in2;  /* device, limb-planar: b of a cyclic product or BLAS op (axpy: y) */
+  const uint32_t* alpha;  /* host, limbs words: axpy's scalar; ignored otherwise */
 } moma_ntt_job_t;
 
 typedef struct moma_batch* moma_batch_t;

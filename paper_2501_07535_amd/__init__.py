@@ -85,10 +85,10 @@ _lib.moma_ntt_default_schedule.argtypes = [ctypes.c_uint32, ctypes.c_uint32, cty
 
 class _Job(ctypes.Structure):
     _fields_ = [("q", _u32p), ("omega", _u32p), ("n", ctypes.c_uint64), ("limbs", ctypes.c_uint32),
-                ("kind", ctypes.c_uint32), ("d_in", _vp), ("d_out", _vp), ("d_in2", _vp)]
+                ("kind", ctypes.c_uint32), ("d_in", _vp), ("d_out", _vp), ("d_in2", _vp), ("alpha", _u32p)]
 
 
-JOB_FORWARD, JOB_INVERSE, JOB_CYCLIC_MUL = 0, 1, 2
+JOB_FORWARD, JOB_INVERSE, JOB_CYCLIC_MUL, JOB_VADD, JOB_VSUB, JOB_VMUL, JOB_AXPY = range(7)
 
 
 _lib.moma_batch_create.argtypes = [ctypes.POINTER(_Job), ctypes.c_uint32, ctypes.POINTER(_vp)]
@@ -350,13 +350,15 @@ def ntt_get_schedule(q: int, omega: int, n: int, limbs: int) -> tuple:
 
 
 class Batch:
-    """Many transforms run as one graph launch.
+    """Many transforms and BLAS calls run as one graph launch.
 
     jobs: iterable of (x, out, q, omega, kind) with x / out limb-planar device
     tensors of shape (limbs, n) (out may be x).  kind is JOB_FORWARD (or False),
-    JOB_INVERSE (or True) or JOB_CYCLIC_MUL; for a cyclic product x is the pair
-    (a, b).  The batch keeps references to the tensors; run() recomputes every
-    job from its current inputs.
+    JOB_INVERSE (or True), JOB_CYCLIC_MUL or a BLAS kind (JOB_VADD, JOB_VSUB,
+    JOB_VMUL, JOB_AXPY).  For a cyclic product and the BLAS kinds x is the
+    pair (a, b) (axpy: (x, y)); for axpy the fourth entry is alpha, for the
+    other BLAS kinds it is ignored.  The batch keeps references to the tensors;
+    run() recomputes every job from its current inputs.
     """
 
     def __init__(self, jobs):
@@ -364,21 +366,26 @@ class Batch:
         recs = []
         for x, out, q, omega, kind in jobs:
             kind = int(kind)
-            if kind not in (JOB_FORWARD, JOB_INVERSE, JOB_CYCLIC_MUL):
+            if kind not in range(7):
                 raise ValueError(f"unknown job kind {kind}")
-            if kind == JOB_CYCLIC_MUL:
+            pair = kind == JOB_CYCLIC_MUL or kind >= JOB_VADD
+            x2 = None
+            if pair:
                 x, x2 = x
                 _dev(x2, "b")
                 if x2.shape != x.shape:
-                    raise ValueError("a and b must have the same shape")
+                    raise ValueError("the two inputs must have the same shape")
                 self._keep.append(x2)
             _dev(x, "x")
             _dev(out, "out")
             limbs, n = x.shape
-            qw, ww = _words(q, limbs), _words(omega, limbs)
-            self._keep += [x, out, qw, ww]
+            qw = _words(q, limbs)
+            ww = _words(omega if (kind < JOB_VADD and omega is not None) else 0, limbs)
+            aw = _words(omega, limbs) if kind == JOB_AXPY else None
+            self._keep += [x, out, qw, ww, aw]
             recs.append(_Job(ctypes.cast(qw, _u32p), ctypes.cast(ww, _u32p), n, limbs, kind, x.data_ptr(),
-                             out.data_ptr(), x2.data_ptr() if kind == JOB_CYCLIC_MUL else None))
+                             out.data_ptr(), x2.data_ptr() if pair else None,
+                             ctypes.cast(aw, _u32p) if aw is not None else None))
         arr = (_Job * len(recs))(*recs)
         h = _vp()
         _check(_lib.moma_batch_create(arr, len(recs), ctypes.byref(h)))

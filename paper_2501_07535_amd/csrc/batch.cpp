@@ -53,10 +53,19 @@ struct PlaneCopy {
   uint64_t words;
 };
 
+struct BlasLaunch {
+  int op, L;
+  uint32_t variant, nitems;
+  const void* d_recs;
+  const void* d_consts;
+  const uint2* d_items;
+};
+
 struct BatchImpl {
   std::vector<std::shared_ptr<NttPlan>> plans;  // keep tables alive
   std::vector<void*> dev_allocs;
   std::vector<BatchLaunch> launches;
+  std::vector<BlasLaunch> blas;
   std::vector<ZeroFill> fills;
   std::vector<PlaneCopy> copy_in, copy_out;
   std::vector<ZeroFill> stage_tops;
@@ -132,11 +141,52 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       g.lds[ph] = std::max(g.lds[ph], bytes);
     }
   };
+  // BLAS jobs: per (op, compute limbs, vmul variant) the job records, their
+  // constants and the (record, 256-element block) items
+  struct BGroup {
+    std::vector<BlasJobRec> recs;
+    std::vector<uint8_t> consts;
+    std::vector<uint2> items;
+  };
+  std::map<std::tuple<int, int, uint32_t>, BGroup> bgroups;
   for (uint32_t j = 0; j < njobs; j++) {
     const moma_ntt_job_t& job = jobs[j];
     const std::string tag = "job " + std::to_string(j) + ": ";
+    if (job.kind > MOMA_JOB_AXPY) return set_error(MOMA_E_ARG, tag + "unknown job kind");
+    if (job.kind >= MOMA_JOB_VADD) {
+      const int op = (int)job.kind - (int)MOMA_JOB_VADD;  // OP_VADD .. OP_AXPY
+      std::shared_ptr<FieldEntry> fe;
+      int rc = build_field(job.q, job.limbs, &fe);
+      if (rc) return set_error(rc, tag + g_detail);
+      if (job.n > (1ull << 31)) return set_error(MOMA_E_ARG, tag + "n must be <= 2^31");
+      if (job.n == 0) continue;
+      if (!job.d_in || !job.d_in2 || !job.d_out) return set_error(MOMA_E_ARG, tag + "NULL buffer");
+      BlasArgs a;
+      memset(&a, 0, sizeof(a));
+      a.a = job.d_in;
+      a.b = job.d_in2;
+      a.out = job.d_out;
+      a.n = job.n;
+      a.ls = (uint32_t)fe->f.Ls;
+      if (op == OP_VMUL) a.variant = vmul_variant(fe->f.L);
+      if (op == OP_AXPY) {
+        rc = axpy_alpha(*fe, job.alpha, job.limbs, a.alpha_m);
+        if (rc) return set_error(rc, tag + g_detail);
+      }
+      BGroup& g = bgroups[std::make_tuple(op, fe->f.L, a.variant)];
+      const uint32_t rec = (uint32_t)g.recs.size();
+      g.recs.push_back({job.d_in, job.d_in2, job.d_out, job.n});
+      size_t cb = blas_consts_bytes(fe->f.L), off = g.consts.size();
+      g.consts.resize(off + cb);
+      blas_fill_consts(fe->f, a, g.consts.data() + off);
+      const uint64_t blocks = (job.n + 255) / 256;
+      if (g.items.size() + blocks > 0x7fffffffull) return set_error(MOMA_E_UNSUPPORTED, tag + "too many blocks");
+      for (uint64_t k = 0; k < blocks; k++) g.items.push_back(make_uint2(rec, (uint32_t)k));
+      if (fe->f.Ls > fe->f.L && job.d_out != job.d_in && job.d_out != job.d_in2)
+        b.fills.push_back({job.d_out, job.n, fe->f.L, fe->f.Ls});
+      continue;
+    }
     if (!job.d_in || !job.d_out) return set_error(MOMA_E_ARG, tag + "NULL buffer");
-    if (job.kind > MOMA_JOB_CYCLIC_MUL) return set_error(MOMA_E_ARG, tag + "unknown job kind");
     if (job.kind == MOMA_JOB_CYCLIC_MUL && !job.d_in2) return set_error(MOMA_E_ARG, tag + "NULL second input");
     std::shared_ptr<NttPlan> p;
     int rc = get_plan(job.q, job.omega, job.n, job.limbs, &p);
@@ -251,6 +301,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       bl.threads = std::get<2>(kv.first);
       bl.lds = kv.second.lds[ph];
       bl.nitems = (uint32_t)items.size();
+      if (items.size() > 0x7fffffffull) return set_error(MOMA_E_UNSUPPORTED, "batch phase has too many tiles");
       bl.grid = bl.nitems;  // one workgroup per item
       bl.d_passes = (const NttPassArgs*)dev_recs[kv.first].first;
       bl.d_consts = dev_recs[kv.first].second;
@@ -259,12 +310,35 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       b.items += bl.nitems;
     }
   }
+  for (auto& kv : bgroups) {
+    BGroup& g = kv.second;
+    BlasLaunch bl;
+    bl.op = std::get<0>(kv.first);
+    bl.L = std::get<1>(kv.first);
+    bl.variant = std::get<2>(kv.first);
+    bl.nitems = (uint32_t)g.items.size();
+    void *dr = nullptr, *dc = nullptr, *di = nullptr;
+    int rc = dev_upload(b, g.recs.data(), g.recs.size() * sizeof(BlasJobRec), &dr);
+    if (!rc) rc = dev_upload(b, g.consts.data(), g.consts.size(), &dc);
+    if (!rc) rc = dev_upload(b, g.items.data(), g.items.size() * sizeof(uint2), &di);
+    if (rc) return rc;
+    bl.d_recs = dr;
+    bl.d_consts = dc;
+    bl.d_items = (const uint2*)di;
+    b.blas.push_back(bl);
+    b.items += bl.nitems;
+  }
   for (const BatchLaunch& bl : b.launches) ntt_batch_prepare(bl.L, bl.radix_log, bl.lds);
   // capture the launches into one graph
   if (hipStreamCreate(&b.cap)) return hip_fail(1, "batch stream");
   if (hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal)) return hip_fail(1, "begin capture");
   int err = 0;
+  for (const BlasLaunch& bl : b.blas) {
+    err = launch_blas_batch(bl.op, bl.L, bl.variant, bl.d_recs, bl.d_consts, bl.d_items, bl.nitems, b.cap);
+    if (err) break;
+  }
   for (const PlaneCopy& c : b.copy_in) {
+    if (err) break;
     err = launch_copy_words(c.dst, c.src, c.words, b.cap);
     if (err) break;
   }
@@ -329,8 +403,8 @@ int moma_batch_run(moma_batch_t b, void* stream) {
 int moma_batch_info(moma_batch_t b, uint32_t* launches, uint64_t* items) {
   if (!b) return set_error(MOMA_E_ARG, "batch is NULL");
   if (launches)
-    *launches = (uint32_t)(b->impl.launches.size() + b->impl.fills.size() + b->impl.copy_in.size() +
-                           b->impl.stage_tops.size() + b->impl.copy_out.size());
+    *launches = (uint32_t)(b->impl.launches.size() + b->impl.blas.size() + b->impl.fills.size() +
+                           b->impl.copy_in.size() + b->impl.stage_tops.size() + b->impl.copy_out.size());
   if (items) *items = b->impl.items;
   return MOMA_OK;
 }

@@ -4,8 +4,11 @@
 // consecutive words (256 bytes), so every access is fully coalesced.  vadd and
 // vsub are HBM-bound (3 * 4L bytes per element against ~3L VALU ops); vmul and
 // axpy carry an L-limb modular multiply per element.
+#include <string.h>
+
 #include "common.hpp"
 #include "limb.hpp"
+#include "plan.hpp"
 
 namespace moma {
 
@@ -162,6 +165,123 @@ int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s) {
   switch (f.L) {
 #define CASE(LL) \
   case LL: return launch_blas_op<LL>(op, f, a, s);
+    MOMA_FOR_EACH_L(CASE)
+#undef CASE
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- batched
+//
+// Many BLAS calls of one (op, compute limbs, product variant) in one launch:
+// workgroup w runs item w = (job record, block of 256 elements); every record
+// carries its own vectors, length and modulus constants.  Items are ordered
+// job by job, so the blocks of a vector stay together.
+
+template <int L, int OP, bool KARA>
+__global__ __launch_bounds__(256) void blas_batch_kernel(const BlasJobRec* __restrict__ recs,
+                                                         const BlasC<L>* __restrict__ consts,
+                                                         const uint2* __restrict__ items, u32 nitems) {
+  const u32 w = blockIdx.x;
+  if (w >= nitems) return;
+  const uint2 it = items[w];
+  const BlasJobRec r = recs[it.x];
+  const BlasC<L> c = consts[it.x];
+  const u64 i = (u64)it.y * blockDim.x + threadIdx.x;
+  if (i >= r.n) return;
+  const u64 n = r.n;
+  const int lim = c.ls < (u32)L ? (int)c.ls : L;
+  u32 a[L], bb[L], res[L];
+#pragma unroll
+  for (int j = 0; j < L; j++) {
+    a[j] = j < lim ? r.a[(u64)j * n + i] : 0u;
+    bb[j] = j < lim ? r.b[(u64)j * n + i] : 0u;
+  }
+  if (OP == OP_VADD) {
+    mod_add<L>(res, a, bb, c.q);
+  } else if (OP == OP_VSUB) {
+    mod_sub<L>(res, a, bb, c.q);
+  } else if (OP == OP_VMUL) {
+    barrett_mul<L, KARA>(res, a, bb, c.bc);
+  } else {
+    u32 t[L];
+    mont_mul<L>(t, a, c.alpha_m, c.q, c.qinv);
+    mod_add<L>(res, t, bb, c.q);
+  }
+#pragma unroll
+  for (int j = 0; j < L; j++)
+    if (j < lim) r.out[(u64)j * n + i] = res[j];
+}
+
+template <int L>
+static BlasC<L> blas_consts(const FieldRaw& f, const BlasArgs& a) {
+  BlasC<L> c;
+  memset(&c, 0, sizeof(c));
+  for (int j = 0; j < L; j++) {
+    c.q[j] = f.q[j];
+    c.bc.qn[j] = f.qn[j];
+    c.bc.mu[j] = f.mu[j];
+    c.alpha_m[j] = a.alpha_m[j];
+  }
+  c.qinv = f.qinv;
+  c.bc.d = f.d;
+  c.ls = a.ls;
+  return c;
+}
+
+size_t blas_consts_bytes(int L) {
+  switch (L) {
+#define CASE(LL) \
+  case LL: return sizeof(BlasC<LL>);
+    MOMA_FOR_EACH_L(CASE)
+#undef CASE
+  }
+  return 0;
+}
+
+void blas_fill_consts(const FieldRaw& f, const BlasArgs& a, void* dst) {
+  switch (f.L) {
+#define CASE(LL)                                  \
+  case LL: {                                      \
+    BlasC<LL> c = blas_consts<LL>(f, a);          \
+    memcpy(dst, &c, sizeof(c));                   \
+    return;                                       \
+  }
+    MOMA_FOR_EACH_L(CASE)
+#undef CASE
+  }
+}
+
+template <int L, int OP, bool KARA>
+static int launch_blas_batch_LOK(const void* recs, const void* consts, const uint2* items, uint32_t nitems,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL((blas_batch_kernel<L, OP, KARA>), dim3(nitems), dim3(256), 0, s, (const BlasJobRec*)recs,
+                     (const BlasC<L>*)consts, items, nitems);
+  return (int)hipGetLastError();
+}
+
+template <int L>
+static int launch_blas_batch_L(int op, uint32_t variant, const void* recs, const void* consts, const uint2* items,
+                               uint32_t nitems, hipStream_t s) {
+  switch (op) {
+    case OP_VADD: return launch_blas_batch_LOK<L, OP_VADD, false>(recs, consts, items, nitems, s);
+    case OP_VSUB: return launch_blas_batch_LOK<L, OP_VSUB, false>(recs, consts, items, nitems, s);
+    case OP_VMUL:
+      if constexpr (L >= 2) {
+        if (variant == 1) return launch_blas_batch_LOK<L, OP_VMUL, true>(recs, consts, items, nitems, s);
+      }
+      return launch_blas_batch_LOK<L, OP_VMUL, false>(recs, consts, items, nitems, s);
+    case OP_AXPY: return launch_blas_batch_LOK<L, OP_AXPY, false>(recs, consts, items, nitems, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_blas_batch(int op, int L, uint32_t variant, const void* recs, const void* consts, const uint2* items,
+                      uint32_t nitems, hipStream_t s) {
+  if (nitems == 0) return 0;
+  switch (L) {
+#define CASE(LL) \
+  case LL: return launch_blas_batch_L<LL>(op, variant, recs, consts, items, nitems, s);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }

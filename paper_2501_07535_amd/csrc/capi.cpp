@@ -467,6 +467,27 @@ static int ntt_entry(bool inverse, const uint32_t* q, const uint32_t* omega, uin
 // moma_vmul_set_variant or moma_vmul_tune; schoolbook until then
 static uint32_t g_vmul_variant[kMaxLimbs + 1];
 
+uint32_t vmul_variant(int L) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_vmul_variant[L];
+}
+
+int axpy_alpha(FieldEntry& fe, const uint32_t* alpha, uint32_t limbs, uint32_t* alpha_m) {
+  if (!alpha) return set_error(MOMA_E_ARG, "alpha is NULL");
+  std::vector<uint32_t> key(alpha, alpha + limbs);
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (fe.alpha_key != key) {
+    HBig A = HBig::from_limbs(alpha, (int)limbs);
+    if (HBig::cmp(A, fe.Q) >= 0) return set_error(MOMA_E_ARG, "alpha must be < q");
+    HBig am = HBig::mulmod(A, fe.one_m, fe.Q);
+    fe.alpha_m.assign(kMaxLimbs, 0);
+    am.to_limbs(fe.alpha_m.data(), kMaxLimbs);
+    fe.alpha_key = key;
+  }
+  memcpy(alpha_m, fe.alpha_m.data(), sizeof(uint32_t) * kMaxLimbs);
+  return MOMA_OK;
+}
+
 static int blas_entry(int op, const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* alpha,
                       const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, void* stream) {
   std::shared_ptr<FieldEntry> fe;
@@ -482,23 +503,10 @@ static int blas_entry(int op, const uint32_t* q, uint32_t limbs, uint64_t n, con
   a.out = d_out;
   a.n = n;
   a.ls = (uint32_t)fe->f.Ls;
-  if (op == OP_VMUL) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    a.variant = g_vmul_variant[fe->f.L];
-  }
+  if (op == OP_VMUL) a.variant = vmul_variant(fe->f.L);
   if (op == OP_AXPY) {
-    if (!alpha) return set_error(MOMA_E_ARG, "alpha is NULL");
-    std::vector<uint32_t> key(alpha, alpha + limbs);
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (fe->alpha_key != key) {
-      HBig A = HBig::from_limbs(alpha, (int)limbs);
-      if (HBig::cmp(A, fe->Q) >= 0) return set_error(MOMA_E_ARG, "alpha must be < q");
-      HBig am = HBig::mulmod(A, fe->one_m, fe->Q);
-      fe->alpha_m.assign(kMaxLimbs, 0);
-      am.to_limbs(fe->alpha_m.data(), kMaxLimbs);
-      fe->alpha_key = key;
-    }
-    memcpy(a.alpha_m, fe->alpha_m.data(), sizeof(a.alpha_m));
+    int r = axpy_alpha(*fe, alpha, limbs, a.alpha_m);
+    if (r) return r;
   }
   hipStream_t s = (hipStream_t)stream;
   int e = launch_blas(op, fe->f, a, s);

@@ -64,6 +64,22 @@ int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>
 NttSchedule default_schedule(int L, uint32_t logn);
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s);
 int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s);
+// batched BLAS (blas.hip): one record per job, its constants, and items
+// (record, block of 256 elements)
+struct BlasJobRec {
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t* out;
+  uint64_t n;
+};
+size_t blas_consts_bytes(int L);
+void blas_fill_consts(const FieldRaw& f, const BlasArgs& a, void* dst);
+int launch_blas_batch(int op, int L, uint32_t variant, const void* recs, const void* consts, const uint2* items,
+                      uint32_t nitems, hipStream_t s);
+// vmul's product variant for a compute limb count (capi.cpp)
+uint32_t vmul_variant(int L);
+// alpha (storage limbs words) in Montgomery form for axpy, validated < q
+int axpy_alpha(FieldEntry& fe, const uint32_t* alpha, uint32_t limbs, uint32_t* alpha_m);
 // n pseudo-random residues below q in Ls = f.Ls storage planes (timing inputs for the tuners)
 int fill_random_residues(const FieldRaw& f, uint32_t* d, uint64_t n, uint32_t seed, hipStream_t s);
 int launch_fill_residues(uint32_t* p, uint64_t n, int planes, int top, uint32_t top_mask, uint32_t seed, hipStream_t s);

@@ -60,3 +60,54 @@ def test_batch_rejects_bad_job():
     x = to_dev(mi.residues(f, 64, 8, 1))
     with pytest.raises(moma.MomaError):
         moma.Batch([(x, torch.empty_like(x), f.q, f.root(32), False)])   # root of the wrong order
+
+
+def test_batch_blas_jobs_with_transforms():
+    """vadd / vsub / vmul / axpy jobs of mixed widths and ragged lengths (and a
+    full-width modulus, and in-place outputs) captured with transform jobs in
+    one graph: each output equals the plain call and the oracle."""
+    import oracle
+    import paper_2501_07535_amd as moma
+    kinds = [moma.JOB_VADD, moma.JOB_VSUB, moma.JOB_VMUL, moma.JOB_AXPY]
+    ref = {moma.JOB_VADD: "vadd", moma.JOB_VSUB: "vsub", moma.JOB_VMUL: "vmul"}
+    cases = [(64, None, 1000), (96, None, 257), (256, None, 70001), (256, 256, 4096), (384, None, 1),
+             (512, None, 3000), (768, None, 513), (1024, None, 200), (128, 128, 999), (256, None, 0)]
+    specs, checks, keep = [], [], []
+    f8 = mi.find_prime(256, 0)
+    moma.vmul_set_variant(f8.q, 8, moma.VMUL_KARATSUBA)      # one width runs the Karatsuba products
+    try:
+        for k, (lam, bits, n) in enumerate(cases):
+            f = mi.find_prime(lam, 0, bits=bits) if bits else mi.find_prime(lam, 0)
+            q, L = f.q, f.limbs
+            for kind in kinds:
+                a, b = mi.residues(f, n, L, 700 + k, kind), mi.residues(f, n, L, 750 + k, kind)
+                alpha = mi.scalar_residue(f, 800 + k, kind)
+                da, db = to_dev(a), to_dev(b)
+                inplace = (k + kind) % 3 == 0
+                out = da if inplace else torch.full_like(da, -1)
+                keep += [da, db, out]
+                specs.append(((da, db), out, q, alpha, kind))
+                want = oracle.axpy(q, L, alpha, a, b) if kind == moma.JOB_AXPY else getattr(oracle, ref[kind])(q, L, a, b)
+                checks.append((out, want, a, b, alpha, q, kind, lam, n))
+        # and two transforms in the same graph
+        f = mi.find_prime(256, 0)
+        x = mi.residues(f, 1 << 12, 8, 900)
+        dx = to_dev(x)
+        ox = torch.empty_like(dx)
+        keep += [dx, ox]
+        specs.append((dx, ox, f.q, f.root(1 << 12), moma.JOB_FORWARD))
+        say(f"batch with {len(specs)} jobs (BLAS and transforms)")
+        bt = moma.Batch(specs)
+        bt.run()
+        torch.cuda.synchronize()
+        assert (from_dev(ox) == oracle.ntt_radix2(f.q, 8, f.root(1 << 12), x)).all()
+        for out, want, a, b, alpha, q, kind, lam, n in checks:
+            if n == 0:
+                continue
+            assert (from_dev(out) == want).all(), (lam, kind, n)
+            da, db = to_dev(a), to_dev(b)
+            plain = moma.axpy(alpha, da, db, q) if kind == moma.JOB_AXPY else getattr(moma, ref[kind])(da, db, q)
+            assert (from_dev(plain) == want).all(), (lam, kind, n)
+        bt.close()
+    finally:
+        moma.vmul_set_variant(f8.q, 8, moma.VMUL_SCHOOLBOOK)
