@@ -179,7 +179,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the transform path is "
-              "single-GPU in this build", file=sys.stderr)
+              "single-GPU (the multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
         sweep(args)
@@ -277,6 +277,8 @@ def main():
     if not args.no_batch:
         batch = batch_vs_plain(args.batch_jobs, args.batch_reps)
 
+    small = None if args.forward_only else small_call_latency(moma, torch, stream)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(q, L, w, x, n, logn, args.cpu_seconds)
@@ -315,6 +317,7 @@ def main():
                    "roundtrip_exact": roundtrip, "sampled_vs_oracle": sampled_ok,
                    "steady_state": steady,
                    "cyclic_product": cyc,
+                   "n2e12_single_call": small,
                    "batched_vs_plain_speedup": batch["speedup"] if batch else None,
                    "batch": batch},
     }
@@ -338,6 +341,39 @@ def measured_traffic(lam, logn, schedule, stages):
     if h.hexdigest() != rec["kernel_sources_sha256"] or not same:
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def small_call_latency(moma, torch, stream, reps=100, warmup=10):
+    """The 4096-point 256-bit forward and inverse transform as single calls:
+    median time per call over `reps` calls after `warmup`, each call bracketed
+    by its own events (latency, not throughput), and the round trip."""
+    import oracle
+    f = mi.find_prime(256, 0)
+    L, n, q = f.limbs, 1 << 12, f.q
+    w = f.root(n)
+    x = mi.residues(f, n, L, 900, 1)
+    dx = torch.from_numpy(mi.to_planar(x).view(np.int32)).to(stream.device)
+    dy, dz = torch.empty_like(dx), torch.empty_like(dx)
+    moma.ntt_prepare(q, w, n, L)
+    res = {"schedule": list(moma.ntt_get_schedule(q, w, n, L))}
+    for name, fn in (("fwd_us", lambda: moma.ntt_fwd(dx, q, w, out=dy)),
+                     ("inv_us", lambda: moma.ntt_inv(dy, q, w, out=dz))):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1) * 1e3)
+        res[name] = round(float(np.median(t)), 3)
+    res["roundtrip_exact"] = bool(torch.equal(dz, dx))
+    got = mi.from_planar(dy.cpu().numpy().view(np.uint32))
+    res["fwd_vs_oracle"] = bool((got == oracle.ntt_radix2(q, L, w, x)).all())
+    return res
 
 
 def cyclic_product(moma, torch, stream, da, db, dc, q, w, n, warmup, reps):

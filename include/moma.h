@@ -65,7 +65,7 @@ enum {
   MOMA_E_ROOT = -3,        /* omega does not have order exactly n         */
   MOMA_E_NOMEM = -4,       /* device allocation failed                    */
   MOMA_E_HIP = -5,         /* a HIP runtime call failed                   */
-  MOMA_E_UNSUPPORTED = -6  /* valid request this build cannot run          */
+  MOMA_E_UNSUPPORTED = -6  /* valid request the library cannot run         */
 };
 
 #define MOMA_MIN_LIMBS 2
