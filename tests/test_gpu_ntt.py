@@ -125,3 +125,32 @@ def test_ntt_full_size_sampled(lam, logn):
     assert (got == oracle.ntt_direct(q, L, w, x, ks)).all()
     z = moma.ntt_inv(y, q, w)
     assert torch.equal(z, dx)
+
+
+@pytest.mark.parametrize("sched", [(10, 5, 256, 2), (11, 5, 256, 2)])
+def test_headline_size_in_the_benchmarked_launch_shape(sched):
+    """256 bits, n = 2^20, in the launch shapes the benchmark times (the
+    autotuner's picks): sampled outputs against the definition, the whole
+    vector against the oracle's fast transform, the round trip, and the
+    in-place call."""
+    import oracle
+    import torch
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(256, 0)
+    L, n, q = 8, 1 << 20, f.q
+    w = f.root(n)
+    x = mi.residues(f, n, L, 2, 20)          # the benchmark's input stream
+    moma.ntt_set_schedule(q, w, n, L, sched)
+    try:
+        say(f"headline shape {sched}")
+        dx = to_dev(x)
+        y = moma.ntt_fwd(dx, q, w)
+        ks = np.array([0, 1, 12345, n // 3, n - 1], dtype=np.int64)
+        got = mi.from_planar(y[:, torch.from_numpy(ks).to("cuda:0")].cpu().numpy().view(np.uint32))
+        assert (got == oracle.ntt_direct(q, L, w, x, ks)).all()
+        assert (from_dev(y) == oracle.ntt_radix2(q, L, w, x)).all()
+        assert torch.equal(moma.ntt_inv(y, q, w), dx)
+        moma.ntt_fwd(dx, q, w, out=dx)
+        assert torch.equal(dx, y)
+    finally:
+        moma.ntt_set_schedule(q, w, n, L, None)
