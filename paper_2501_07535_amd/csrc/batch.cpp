@@ -99,10 +99,12 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     std::map<uint32_t, std::vector<std::pair<uint64_t, uint2>>> items;  // phase -> (cost, item)
     std::map<uint32_t, size_t> lds;                                     // phase -> max tile bytes
   };
-  // key: (compute limbs, register radix, threads) of the job's plan schedule,
-  // and whether the pass multiplies two inputs (first inverse pass of a
-  // cyclic product: a kernel variant of its own)
-  typedef std::tuple<int, uint32_t, uint32_t, bool> GKey;
+  // key: (compute limbs, register radix, threads) of the job's schedule,
+  // whether the pass multiplies two inputs (first inverse pass of a cyclic
+  // product: a kernel variant of its own), and the tile's LDS bytes (a launch
+  // reserves its largest tile for every workgroup, so mixing sizes would cut
+  // the occupancy of the smaller tiles)
+  typedef std::tuple<int, uint32_t, uint32_t, bool, size_t> GKey;
   std::map<GKey, Group> groups;
   NttConsts none;
   memset(&none, 0, sizeof(none));
@@ -114,7 +116,8 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     size_t cb = ntt_consts_bytes(f.L);
     for (size_t i = 0; i < passes.size(); i++) {
       const NttPass& ps = passes[i];
-      Group& g = groups[GKey(f.L, sched.radix_log, sched.threads, i == 0 && in2 != nullptr)];
+      const size_t tile_bytes = ((size_t)1 << (ps.k + ps.logc)) * f.L * sizeof(uint32_t);
+      Group& g = groups[GKey(f.L, sched.radix_log, sched.threads, i == 0 && in2 != nullptr, tile_bytes)];
       NttPassArgs a{};
       a.in = (i == 0) ? in : (i == 1 ? first_out : out);
       a.in2 = (i == 0) ? in2 : nullptr;
