@@ -205,10 +205,10 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     }
     // A plan's own schedule is chosen for a lone call, where small transforms
     // want small tiles to spread over the chip.  In a batch the other jobs
-    // fill the chip, so jobs below 2^18 points use the fixed rule's large
-    // tiles (fewer passes and workgroups); larger jobs keep their schedule.
+    // fill the chip, so jobs below 2^18 points take large tiles (fewer passes
+    // and workgroups); larger jobs keep their schedule.
     if (p->n < (1ull << 18)) {
-      NttSchedule ds = default_schedule(f.L, p->logn);
+      NttSchedule ds = batch_schedule(f.L, p->logn);
       std::vector<NttPass> dp;
       std::string keep = g_detail;
       if (plan_passes(f.L, p->logn, ds, &dp) == MOMA_OK) {

@@ -153,28 +153,20 @@ int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>
   return MOMA_OK;
 }
 
-// Default launch shape, first feasible of: one pass when the whole transform
-// fits a 64 KiB tile; otherwise 32 KiB tiles (several workgroups per CU) with
-// 16, 8 or 4 coalesced columns.  Radix-4 register units where the VGPR budget
-// allows, and enough threads to give each one or two units per round.
-NttSchedule default_schedule(int L, uint32_t logn) {
-  auto lg = [](uint32_t words) {
-    uint32_t t = 0;
-    while ((2u << t) <= words) t++;
-    return t;
-  };
-  uint32_t t64 = lg(16384u / (uint32_t)L), t32 = lg(8192u / (uint32_t)L);
+// First feasible of an ordered list of (tile_log, col_log), with the radix
+// and thread count filled in by rule: radix 4 where the VGPR budget allows,
+// and enough threads to give each one or two units per round.
+static NttSchedule first_feasible(int L, uint32_t logn, const std::vector<std::pair<uint32_t, uint32_t>>& shapes) {
   uint32_t radix = std::min(2u, max_radix_log(L));
-  std::vector<NttSchedule> cands;
-  if (logn <= t64) cands.push_back({logn, 0, 0, radix});
-  for (uint32_t cl : {4u, 3u, 2u}) cands.push_back({t32, cl, 0, radix});
-  for (uint32_t cl : {4u, 3u, 2u, 1u}) cands.push_back({t64, cl, 0, radix});
   std::string keep = g_detail;
-  for (NttSchedule s : cands) {
+  NttSchedule last{};
+  for (auto tc : shapes) {
+    NttSchedule s{tc.first, tc.second, 0, radix};
     uint32_t e = std::min(logn, s.tile_log);
     uint32_t units = 1u << (e > s.radix_log ? e - s.radix_log : 0);
     uint32_t t = std::min(units > 256 ? 256u : units, ntt_max_threads(L, s.radix_log));
     s.threads = t < 64 ? 64 : (t + 63) / 64 * 64;
+    last = s;
     std::vector<NttPass> ps;
     if (plan_passes(L, logn, s, &ps) == MOMA_OK) {
       g_detail = keep;
@@ -182,7 +174,38 @@ NttSchedule default_schedule(int L, uint32_t logn) {
     }
   }
   g_detail = keep;
-  return cands.back();
+  return last;
+}
+
+static uint32_t tile_log_for(uint32_t words) {
+  uint32_t t = 0;
+  while ((2u << t) <= words) t++;
+  return t;
+}
+
+// Default launch shape, first feasible of: one pass when the whole transform
+// fits a 64 KiB tile; otherwise 32 KiB tiles (several workgroups per CU) with
+// 16, 8 or 4 coalesced columns, then 64 KiB tiles.
+NttSchedule default_schedule(int L, uint32_t logn) {
+  uint32_t t64 = tile_log_for(16384u / (uint32_t)L), t32 = tile_log_for(8192u / (uint32_t)L);
+  std::vector<std::pair<uint32_t, uint32_t>> shapes;
+  if (logn <= t64) shapes.push_back({logn, 0});
+  for (uint32_t cl : {4u, 3u, 2u}) shapes.push_back({t32, cl});
+  for (uint32_t cl : {4u, 3u, 2u, 1u}) shapes.push_back({t64, cl});
+  return first_feasible(L, logn, shapes);
+}
+
+// Shape for a small job inside a batch, where other jobs fill the chip: one
+// pass when the transform fits a 64 KiB tile, else the largest tiles (fewest
+// passes) with 32 or 16 columns.
+NttSchedule batch_schedule(int L, uint32_t logn) {
+  uint32_t t64 = tile_log_for(16384u / (uint32_t)L), t32 = tile_log_for(8192u / (uint32_t)L);
+  std::vector<std::pair<uint32_t, uint32_t>> shapes;
+  if (logn <= t64) shapes.push_back({logn, 0});
+  for (uint32_t cl : {5u, 4u}) shapes.push_back({t64, cl});
+  for (uint32_t cl : {5u, 4u, 3u, 2u}) shapes.push_back({t32, cl});
+  for (uint32_t cl : {3u, 2u, 1u}) shapes.push_back({t64, cl});
+  return first_feasible(L, logn, shapes);
 }
 
 NttSchedule initial_schedule(int L, uint32_t logn) {

@@ -62,6 +62,7 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
 uint32_t max_radix_log(int L);
 int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out);
 NttSchedule default_schedule(int L, uint32_t logn);
+NttSchedule batch_schedule(int L, uint32_t logn);
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s);
 int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s);
 // batched BLAS (blas.hip): one record per job, its constants, and items
