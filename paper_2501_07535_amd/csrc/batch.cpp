@@ -205,9 +205,10 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     }
     // A plan's own schedule is chosen for a lone call, where small transforms
     // want small tiles to spread over the chip.  In a batch the other jobs
-    // fill the chip, so jobs below 2^18 points take large tiles (fewer passes
-    // and workgroups); larger jobs keep their schedule.
-    if (p->n < (1ull << 18)) {
+    // fill the chip, so jobs up to 2^18 points take large tiles (fewer passes
+    // and workgroups); larger jobs keep their schedule, which measured faster
+    // for them (2^24 points, and 1024-bit moduli at 2^20).
+    if (p->n <= (1ull << 18)) {
       NttSchedule ds = batch_schedule(f.L, p->logn);
       std::vector<NttPass> dp;
       std::string keep = g_detail;
