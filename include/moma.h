@@ -174,7 +174,8 @@ int moma_ntt_describe(const uint32_t* q, const uint32_t* omega, uint64_t n, uint
  *               passes run tile_log - col_log stages each;
  *   threads   - threads per workgroup, a multiple of 64 in [64, 1024];
  *   radix_log - stages each thread runs in registers per LDS round trip
- *               (radix 2, 4 or 8; radix 8 up to 5 limbs, radix 4 up to 10).
+ *               (radix 2, 4, 8 or 16; radix 16 up to 2 limbs, radix 8 up to 5,
+ *               radix 4 up to 10).
  * Every schedule computes the same result; only speed differs.
  */
 typedef struct moma_ntt_schedule {

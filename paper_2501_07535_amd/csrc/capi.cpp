@@ -115,6 +115,7 @@ int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* 
 static std::map<std::vector<uint32_t>, std::shared_ptr<NttPlan>> g_plans;
 
 uint32_t max_radix_log(int L) {
+  if (L <= kMaxLimbsRadix16) return 4u;
   return L <= kMaxLimbsRadix8 ? 3u : (L <= kMaxLimbsRadix4 ? 2u : 1u);
 }
 

@@ -15,9 +15,10 @@ constexpr int digit_bits(int L) { return L <= 28 ? 29 : 28; }
 constexpr int digit_count(int L) { return (32 * L - 2 + digit_bits(L) - 1) / digit_bits(L); }
 constexpr int digit_stride(int L) { return digit_count(L) + (digit_count(L) & 1); }  // table words per entry
 
-// widest limb counts that get radix-4 / radix-8 register units
+// widest limb counts that get radix-4 / radix-8 / radix-16 register units
 constexpr int kMaxLimbsRadix4 = 10;
 constexpr int kMaxLimbsRadix8 = 5;
+constexpr int kMaxLimbsRadix16 = 2;
 
 // Constants of one modulus, sized for the largest limb count; the launchers copy
 // the first L words of each array into a compile-time sized kernel argument.

@@ -332,9 +332,11 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
   u32 sg = 0;
   while (sg < t.k) {
     u32 rem = t.k - sg;
-    const u32 rr = (R >= 3 && rem >= 3) ? 3 : ((R >= 2 && rem >= 2) ? 2 : 1);
+    const u32 rr = rem < (u32)R ? rem : (u32)R;
     const bool store = fuse && sg + rr == t.k;
-    if (rr == 3) {
+    if (rr == 4) {
+      round_at<L, (R >= 4 ? 4 : 1)>(lds, t, sg, a, c, store);
+    } else if (rr == 3) {
       round_at<L, (R >= 3 ? 3 : 1)>(lds, t, sg, a, c, store);
     } else if (rr == 2) {
       round_at<L, (R >= 2 ? 2 : 1)>(lds, t, sg, a, c, store);
@@ -533,6 +535,9 @@ int launch_pass_L(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a
   if constexpr (L <= kMaxLimbsRadix8) {
     if (radix_log == 3) return launch_pass_LR<L, 3>(c, a, threads, tiles, s);
   }
+  if constexpr (L <= kMaxLimbsRadix16) {
+    if (radix_log == 4) return launch_pass_LR<L, 4>(c, a, threads, tiles, s);
+  }
   return (int)hipErrorInvalidValue;
 }
 
@@ -561,6 +566,10 @@ int launch_batch_L(uint32_t radix_log, bool mul, uint32_t threads, size_t lds, u
     if (radix_log == 3)
       return launch_batch_LR<L, 3>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
   }
+  if constexpr (L <= kMaxLimbsRadix16) {
+    if (radix_log == 4)
+      return launch_batch_LR<L, 4>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  }
   return (int)hipErrorInvalidValue;
 }
 
@@ -582,6 +591,9 @@ void batch_attr_L(uint32_t radix_log) {
   }
   if constexpr (L <= kMaxLimbsRadix8) {
     if (radix_log == 3) batch_attr_LR<L, 3>();
+  }
+  if constexpr (L <= kMaxLimbsRadix16) {
+    if (radix_log == 4) batch_attr_LR<L, 4>();
   }
 }
 

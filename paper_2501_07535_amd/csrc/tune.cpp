@@ -57,7 +57,7 @@ std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn) {
     bool single = logn <= tl;
     for (uint32_t cl : {2u, 3u, 4u, 5u}) {
       if (single && cl != 2) continue;  // the column count does not apply to one-pass plans
-      for (uint32_t r = 1; r <= 3; r++) {
+      for (uint32_t r = 1; r <= max_radix_log(L); r++) {
         for (uint32_t t : {64u, 128u, 256u, 512u, 1024u}) {
           NttSchedule s{single ? logn : tl, single ? 0u : cl, t, r};
           std::vector<NttPass> ps;
@@ -66,6 +66,11 @@ std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn) {
           uint32_t e = single ? logn : tl;
           uint32_t units = 1u << (e > r ? e - r : 0);
           if (t > 64 && t > units) continue;
+          // a radix-16 unit on passes of fewer than 4 stages runs as radix 8
+          if (r == 4 && std::max_element(ps.begin(), ps.end(), [](const NttPass& x, const NttPass& y) {
+                          return x.k < y.k;
+                        })->k < 4)
+            continue;
           bool dup = false;
           for (const NttSchedule& o : out)
             dup |= o.tile_log == s.tile_log && o.col_log == s.col_log && o.threads == s.threads &&

@@ -8,6 +8,9 @@
   python -m paper_2501_07535_amd.tuning train --db DB.csv [...] --model cm.txt
       train the cost model on every shape (the model a package ships: new plans
       without timings start from its top-ranked schedule)
+  python -m paper_2501_07535_amd.tuning picks --db DB.csv [...] --model cm.txt --out picks.json
+      the top-1 regret of a saved model on every shape of the database (for the
+      packaged model: the cost of a new plan's first pick on shapes it was trained on)
   python -m paper_2501_07535_amd.tuning widths --db DB.csv [...] --out widths.json
       the autotuned transform time against the bit-width class at fixed sizes,
       and the slowdown per doubling of the width (Section 5.4); no GPU needed
@@ -143,6 +146,30 @@ def train_all(paths, model_path, seed=7, epochs=300, batch=256, lr=3e-3):
                       "model": model_path}), flush=True)
 
 
+def picks(paths, model_path, out):
+    import paper_2501_07535_amd as moma
+    moma.costmodel_load(model_path)
+    by_shape = {}
+    for L, n, s, us in load_rows(paths):
+        by_shape.setdefault((L, n), []).append((s, us))
+    regret, picked = [], {}
+    for shp in sorted(by_shape):
+        cands = by_shape[shp]
+        times = np.array([us for _, us in cands])
+        f = np.array([moma.costmodel_features(shp[0], shp[1], s) for s, _ in cands], np.float32)
+        i = int(np.argmin(moma.costmodel_predict(f)))
+        regret.append(float(times[i] / times.min() - 1))
+        picked[f"{shp[0]},{shp[1]}"] = {"pick": list(cands[i][0]), "regret": round(regret[-1], 4)}
+    r = np.array(regret)
+    report = {"shapes": len(r), "geomean_regret": float(np.exp(np.mean(np.log1p(r))) - 1),
+              "max_regret": float(r.max()), "within_5pct_fraction": float(np.mean(r <= 0.05)),
+              "radix16_picks": sum(1 for v in picked.values() if v["pick"][3] == 4), "by_shape": picked}
+    with open(out, "w") as fh:
+        json.dump(report, fh, indent=1)
+    print(json.dumps({k: v for k, v in report.items() if k != "by_shape"}, indent=1), flush=True)
+    return report
+
+
 def widths(paths, out, logns=(12, 16)):
     """Autotuned (fastest measured) time per bit-width class at fixed n, and the
     slowdown factor of each width doubling 64 -> 128 -> ... -> 1024."""
@@ -194,6 +221,10 @@ def main():
     t.add_argument("--db", nargs="+", required=True)
     t.add_argument("--model", required=True)
     t.add_argument("--epochs", type=int, default=300)
+    p = sub.add_parser("picks")
+    p.add_argument("--db", nargs="+", required=True)
+    p.add_argument("--model", required=True)
+    p.add_argument("--out", required=True)
     w = sub.add_parser("widths")
     w.add_argument("--db", nargs="+", required=True)
     w.add_argument("--out", required=True)
@@ -201,6 +232,8 @@ def main():
     a = ap.parse_args()
     if a.cmd == "train":
         train_all(a.db, a.model, epochs=a.epochs)
+    elif a.cmd == "picks":
+        picks(a.db, a.model, a.out)
     elif a.cmd == "widths":
         widths(a.db, a.out, tuple(int(v) for v in a.logn.split(",")))
     elif a.cmd == "collect":

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 
 def all_schedules():
-    return list(itertools.product(range(5, 15), (2, 3, 4, 5), (64, 128, 256, 512, 1024), (1, 2, 3)))
+    return list(itertools.product(range(5, 15), (2, 3, 4, 5), (64, 128, 256, 512, 1024), (1, 2, 3, 4)))
 
 
 @pytest.mark.parametrize("lam,logn", [(256, 11), (256, 14), (128, 16), (384, 13), (64, 15), (1024, 11)])
