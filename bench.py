@@ -100,7 +100,12 @@ def sweep(args):
         ks = np.array([0, 1, n - 1], dtype=np.int64)
         got = mi.from_planar(dy[:, torch.from_numpy(ks).to(dev)].cpu().numpy().view(np.uint32))
         ok = bool((got == oracle.ntt_direct(q, L, w, x, ks)).all())
-        st = steady_state(moma, torch, stream, dx, q, w, n, L, logn, ks=(1, 4, 16) if logn <= 22 else (1, 2))
+        # batches of up to 64 transforms, as far as 16 GiB of inputs and outputs allow
+        per = 2 * n * 4 * L
+        kmax = max(1, min(64, (16 << 30) // per))
+        kmax = 1 << (kmax.bit_length() - 1)
+        st = steady_state(moma, torch, stream, dx, q, w, n, L, logn,
+                          ks=tuple(sorted({k for k in (1, 4, 16, 64) if k <= kmax} | {kmax})))
         B = n // 2 * logn
         print(json.dumps({"lambda": lam, "limbs": L, "log2_n": logn, "fwd_us": round(us, 2),
                           "gbutterfly_s": round(B / us / 1e3, 3), "steady_state": st,
@@ -431,7 +436,7 @@ def _time_fwd(moma, torch, stream, dx, dy, q, w, warmup, reps):
     return e0.elapsed_time(e1) * 1e3 / reps
 
 
-def steady_state(moma, torch, stream, dx, q, w, n, L, logn, ks=(1, 2, 4, 8, 16)):
+def steady_state(moma, torch, stream, dx, q, w, n, L, logn, ks=(1, 2, 4, 8, 16, 32, 64)):
     """The paper's steady-state protocol (Section 5.1): t_single = t_all / k for a
     batch of k transforms of this size, minimised over k; here each batch is one
     graph launch of the batched executor over k independent buffers."""

@@ -519,7 +519,7 @@ def shutdown():
 
 
 # The cost model trained on this device class's timing database (written by
-# `python -m paper_2501_07535_amd.tuning evaluate --model ...`): loaded at
+# `python -m paper_2501_07535_amd.tuning train --model ...`): loaded at
 # import so that new plans without timings start from its top-ranked
 # schedule.  MOMA_NO_COSTMODEL=1 keeps the fixed default rule instead.
 COSTMODEL_PATH = os.path.join(_HERE, "costmodel_gfx950.txt")
