@@ -18,7 +18,8 @@
  *   at index j*n + i (so a wavefront reads 64 consecutive words per limb).
  *   Inputs must be canonical (each element < q); words of limbs above the
  *   top limb of q must therefore be zero.  Non-canonical inputs give
- *   undefined (but memory-safe) results.
+ *   undefined (but memory-safe) results; the paper assumes reduced operands
+ *   throughout (Section 2.1).  The input check below finds them.
  *
  * Preconditions checked on the host before anything is enqueued
  *   2 <= limbs <= 32; q odd, q >= 3, bitlen(q) <= 32*limbs.  The paper's
@@ -78,6 +79,26 @@ const char* moma_strerror(int code);
 const char* moma_last_error_detail(void);
 /* Library version string. */
 const char* moma_version(void);
+
+/*
+ * Input check (the canonical-input precondition of Section 2.1: every operand
+ * is already reduced mod q).
+ *   moma_check_canonical: *bad_out = the number of elements of the
+ *     limb-planar vector d_x (`limbs` planes of n words, n <= 2^31) whose
+ *     value is >= q.  Runs a counting kernel on `stream`, then waits for that
+ *     stream; allocates and frees a small device buffer per call.  Errors:
+ *     MOMA_E_ARG (NULL pointer, n too large), the modulus errors of the other
+ *     calls, MOMA_E_NOMEM, MOMA_E_HIP.
+ *   moma_set_input_check: on != 0 makes every BLAS, transform, cyclic product
+ *     and batch run count its inputs first and fail with MOMA_E_ARG, before
+ *     enqueueing anything, when an input holds a non-canonical element.  Each
+ *     checked call then waits for its stream, so this is a debugging mode.
+ *     The environment variable MOMA_CHECK_INPUTS=1 turns it on at start-up;
+ *     the default is off.
+ */
+int moma_check_canonical(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_x, uint64_t* bad_out,
+                         void* stream);
+int moma_set_input_check(int on);
 
 /*
  * Elementwise modular BLAS (paper Section 2.3; ring operations of Section 2.1).

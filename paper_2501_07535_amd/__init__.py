@@ -65,6 +65,11 @@ _lib.moma_ntt_prepare.restype = ctypes.c_int
 _lib.moma_ntt_describe.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _u32p, _u32p, ctypes.c_uint32,
                                    _u32p]
 _lib.moma_ntt_describe.restype = ctypes.c_int
+_lib.moma_check_canonical.argtypes = [_u32p, ctypes.c_uint32, ctypes.c_uint64, _vp, ctypes.POINTER(ctypes.c_uint64),
+                                      _vp]
+_lib.moma_check_canonical.restype = ctypes.c_int
+_lib.moma_set_input_check.argtypes = [ctypes.c_int]
+_lib.moma_set_input_check.restype = ctypes.c_int
 
 
 class Schedule(ctypes.Structure):
@@ -157,7 +162,7 @@ EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vad
             "moma_tune_db_get", "moma_tune_db_clear", "moma_tune_db_save", "moma_tune_db_load",
             "moma_costmodel_features", "moma_costmodel_train", "moma_costmodel_predict", "moma_costmodel_save",
             "moma_costmodel_load", "moma_costmodel_clear", "moma_mlp_nparams", "moma_mlp_forward", "moma_mlp_grad",
-            "moma_mlp_adam", "moma_shutdown")
+            "moma_mlp_adam", "moma_check_canonical", "moma_set_input_check", "moma_shutdown")
 
 
 class MomaError(RuntimeError):
@@ -255,6 +260,22 @@ def axpy(alpha: int, x, y, q: int, out=None, stream=None):
 
 
 VMUL_SCHOOLBOOK, VMUL_KARATSUBA = 0, 1
+
+
+def check_canonical(x, q: int, stream=None) -> int:
+    """Number of elements of x (a (limbs, n) limb-planar tensor) that are >= q;
+    waits for the stream."""
+    _dev(x, "x")
+    limbs, n = x.shape
+    bad = ctypes.c_uint64(0)
+    _check(_lib.moma_check_canonical(_words(q, limbs), limbs, n, x.data_ptr(), ctypes.byref(bad), _stream(stream)))
+    return int(bad.value)
+
+
+def set_input_check(on: bool):
+    """Debugging mode: every call first counts its non-canonical inputs and fails
+    with MOMA_E_ARG if there are any (each such call waits for its stream)."""
+    _check(_lib.moma_set_input_check(1 if on else 0))
 
 
 def vmul_set_variant(q: int, limbs: int, variant: int):

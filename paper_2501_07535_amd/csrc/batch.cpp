@@ -69,6 +69,14 @@ struct BatchImpl {
   std::vector<ZeroFill> fills;
   std::vector<PlaneCopy> copy_in, copy_out;
   std::vector<ZeroFill> stage_tops;
+  // every job's inputs, counted before a run when the input check is on
+  struct Input {
+    std::shared_ptr<FieldEntry> fe;
+    const uint32_t* x;
+    uint64_t n;
+    uint32_t job;
+  };
+  std::vector<Input> inputs;
   uint64_t items = 0;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -187,6 +195,8 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       for (uint64_t k = 0; k < blocks; k++) g.items.push_back(make_uint2(rec, (uint32_t)k));
       if (fe->f.Ls > fe->f.L && job.d_out != job.d_in && job.d_out != job.d_in2)
         b.fills.push_back({job.d_out, job.n, fe->f.L, fe->f.Ls});
+      b.inputs.push_back({fe, job.d_in, job.n, j});
+      b.inputs.push_back({fe, job.d_in2, job.n, j});
       continue;
     }
     if (!job.d_in || !job.d_out) return set_error(MOMA_E_ARG, tag + "NULL buffer");
@@ -195,6 +205,8 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     int rc = get_plan(job.q, job.omega, job.n, job.limbs, &p);
     if (rc) return set_error(rc, tag + g_detail);
     b.plans.push_back(p);
+    b.inputs.push_back({p->fe, job.d_in, job.n, j});
+    if (job.kind == MOMA_JOB_CYCLIC_MUL) b.inputs.push_back({p->fe, job.d_in2, job.n, j});
     const FieldRaw& f = p->fe->f;
     std::vector<NttPass> passes;
     NttSchedule sched;
@@ -399,6 +411,12 @@ int moma_batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, moma_batch_t* 
 
 int moma_batch_run(moma_batch_t b, void* stream) {
   if (!b) return set_error(MOMA_E_ARG, "batch is NULL");
+  if (input_check_on()) {
+    for (const auto& in : b->impl.inputs) {
+      int rc = check_inputs(in.fe->f, &in.x, 1, in.n, (hipStream_t)stream);
+      if (rc) return set_error(rc, "job " + std::to_string(in.job) + ": " + g_detail);
+    }
+  }
   hipError_t e = hipGraphLaunch(b->impl.exec, (hipStream_t)stream);
   if (e) return hip_fail((int)e, "graph launch");
   return MOMA_OK;

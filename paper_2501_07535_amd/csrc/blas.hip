@@ -343,4 +343,43 @@ int launch_copy_words(uint32_t* dst, const uint32_t* src, uint64_t count, hipStr
   return (int)hipGetLastError();
 }
 
+// Input check: counts the elements of a limb-planar vector that are not
+// canonical, i.e. whose value over all `ls` storage planes is >= q.  Each
+// workgroup writes its own count to partial[blockIdx.x]; there are no atomics.
+struct QWords {
+  u32 w[kMaxLimbs];
+};
+
+__global__ __launch_bounds__(256) void count_noncanonical_kernel(const u32* __restrict__ x, u64 n, int ls, QWords q,
+                                                                 u32* __restrict__ partial) {
+  __shared__ u32 red[256];
+  u32 bad = 0;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+    // compare from the top word down: the first differing word decides
+    int state = 0;  // 0 equal so far, 1 x > q, -1 x < q
+    for (int j = ls - 1; j >= 0; j--) {
+      u32 v = x[(u64)j * n + i];
+      if (state == 0 && v != q.w[j]) state = v > q.w[j] ? 1 : -1;
+    }
+    bad += state >= 0 ? 1u : 0u;
+  }
+  red[threadIdx.x] = bad;
+  __syncthreads();
+  for (u32 s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+int launch_count_noncanonical(const uint32_t* q, int ls, const uint32_t* d_x, uint64_t n, uint32_t* d_partial,
+                              uint32_t blocks, hipStream_t s) {
+  if (ls < 1 || ls > kMaxLimbs || blocks == 0) return (int)hipErrorInvalidValue;
+  QWords qw;
+  memset(&qw, 0, sizeof(qw));
+  for (int j = 0; j < ls; j++) qw.w[j] = q[j];
+  hipLaunchKernelGGL(count_noncanonical_kernel, dim3(blocks), dim3(256), 0, s, d_x, n, ls, qw, d_partial);
+  return (int)hipGetLastError();
+}
+
 }  // namespace moma

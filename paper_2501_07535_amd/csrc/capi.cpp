@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -476,12 +477,57 @@ int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_
   return MOMA_OK;
 }
 
+// ------------------------------------------------------------------ input check
+
+static int g_check_inputs = -1;  // -1: MOMA_CHECK_INPUTS not read yet
+
+bool input_check_on() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_check_inputs < 0) {
+    const char* e = getenv("MOMA_CHECK_INPUTS");
+    g_check_inputs = (e && *e && strcmp(e, "0") != 0) ? 1 : 0;
+  }
+  return g_check_inputs == 1;
+}
+
+int count_noncanonical(const FieldRaw& f, const uint32_t* d_x, uint64_t n, hipStream_t s, uint64_t* bad) {
+  *bad = 0;
+  if (n == 0) return MOMA_OK;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (n + 255) / 256);
+  uint32_t* d_part = nullptr;
+  if (hipMalloc((void**)&d_part, blocks * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, "input check buffer");
+  std::vector<uint32_t> part(blocks, 0);
+  int e = launch_count_noncanonical(f.q, f.Ls, d_x, n, d_part, blocks, s);
+  if (!e) e = (int)hipMemcpyAsync(part.data(), d_part, blocks * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (!e) e = (int)hipStreamSynchronize(s);
+  (void)hipFree(d_part);
+  if (e) return hip_fail(e, "input check");
+  for (uint32_t v : part) *bad += v;
+  return MOMA_OK;
+}
+
+int check_inputs(const FieldRaw& f, const uint32_t* const* d_x, int nx, uint64_t n, hipStream_t s) {
+  for (int i = 0; i < nx; i++) {
+    uint64_t bad = 0;
+    int rc = count_noncanonical(f, d_x[i], n, s, &bad);
+    if (rc) return rc;
+    if (bad)
+      return set_error(MOMA_E_ARG, "input " + std::to_string(i) + " holds " + std::to_string(bad) +
+                                       " elements >= q (input check on)");
+  }
+  return MOMA_OK;
+}
+
 static int ntt_entry(bool inverse, const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
                      const uint32_t* d_in, uint32_t* d_out, void* stream) {
   if (!d_in || !d_out) return set_error(MOMA_E_ARG, "device pointer is NULL");
   std::shared_ptr<NttPlan> p;
   int rc = get_plan(q, omega, n, limbs, &p);
   if (rc) return rc;
+  if (input_check_on()) {
+    rc = check_inputs(p->fe->f, &d_in, 1, n, (hipStream_t)stream);
+    if (rc) return rc;
+  }
   return run_plan(*p, inverse, d_in, d_out, (hipStream_t)stream);
 }
 
@@ -533,6 +579,11 @@ static int blas_entry(int op, const uint32_t* q, uint32_t limbs, uint64_t n, con
     if (r) return r;
   }
   hipStream_t s = (hipStream_t)stream;
+  if (input_check_on()) {
+    const uint32_t* xs[2] = {d_a, d_b};
+    rc = check_inputs(fe->f, xs, 2, n, s);
+    if (rc) return rc;
+  }
   int e = launch_blas(op, fe->f, a, s);
   if (e) return hip_fail(e, "blas launch");
   if (fe->f.Ls > fe->f.L) {
@@ -692,7 +743,29 @@ int moma_ntt_cyclic_mul(const uint32_t* q, const uint32_t* omega, uint64_t n, ui
   std::shared_ptr<NttPlan> p;
   int rc = get_plan(q, omega, n, limbs, &p);
   if (rc) return rc;
+  if (input_check_on()) {
+    const uint32_t* xs[2] = {d_a, d_b};
+    rc = check_inputs(p->fe->f, xs, 2, n, (hipStream_t)stream);
+    if (rc) return rc;
+  }
   return run_cyclic_mul(*p, d_a, d_b, d_out, (hipStream_t)stream);
+}
+
+int moma_check_canonical(const uint32_t* q, uint32_t limbs, uint64_t n, const uint32_t* d_x, uint64_t* bad_out,
+                         void* stream) {
+  if (!bad_out) return set_error(MOMA_E_ARG, "bad_out is NULL");
+  std::shared_ptr<FieldEntry> fe;
+  int rc = build_field(q, limbs, &fe);
+  if (rc) return rc;
+  if (n > (1ull << 31)) return set_error(MOMA_E_ARG, "n must be <= 2^31");
+  if (n && !d_x) return set_error(MOMA_E_ARG, "device pointer is NULL");
+  return count_noncanonical(fe->f, d_x, n, (hipStream_t)stream, bad_out);
+}
+
+int moma_set_input_check(int on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_check_inputs = on ? 1 : 0;
+  return MOMA_OK;
 }
 
 int moma_ntt_prepare(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs) {

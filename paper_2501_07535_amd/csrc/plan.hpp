@@ -84,6 +84,13 @@ int axpy_alpha(FieldEntry& fe, const uint32_t* alpha, uint32_t limbs, uint32_t* 
 // n pseudo-random residues below q in Ls = f.Ls storage planes (timing inputs for the tuners)
 int fill_random_residues(const FieldRaw& f, uint32_t* d, uint64_t n, uint32_t seed, hipStream_t s);
 int launch_fill_residues(uint32_t* p, uint64_t n, int planes, int top, uint32_t top_mask, uint32_t seed, hipStream_t s);
+// per-workgroup counts of the elements >= q over `ls` storage planes
+int launch_count_noncanonical(const uint32_t* q, int ls, const uint32_t* d_x, uint64_t n, uint32_t* d_partial,
+                              uint32_t blocks, hipStream_t s);
+// the input check of every entry point (MOMA_CHECK_INPUTS / moma_set_input_check)
+bool input_check_on();
+int count_noncanonical(const FieldRaw& f, const uint32_t* d_x, uint64_t n, hipStream_t s, uint64_t* bad);
+int check_inputs(const FieldRaw& f, const uint32_t* const* d_x, int nx, uint64_t n, hipStream_t s);
 // tuner (tune.cpp)
 std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn);
 bool tune_db_best(const std::string& dev, int L, uint32_t logn, NttSchedule* out);

@@ -161,3 +161,20 @@ def test_vmul_variant_validation():
     buf = (ctypes.c_float * 2)()
     assert lib.moma_vmul_tune(_w(f.q, 8), 8, 0, 3, buf, None) == moma.MOMA_E_ARG
     assert lib.moma_vmul_tune(_w(f.q, 8), 8, 16, 3, None, None) == moma.MOMA_E_ARG
+
+
+def test_input_check_rejects_bad_arguments_on_the_host():
+    import moma_inputs as mi
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    f = mi.find_prime(256, 0)
+    L, q = f.limbs, f.q
+    bad = ctypes.c_uint64(7)
+    assert lib.moma_check_canonical(_w(q, L), L, 16, DUMMY, None, None) == moma.MOMA_E_ARG
+    assert lib.moma_check_canonical(_w(q, L), L, (1 << 31) + 1, DUMMY, ctypes.byref(bad), None) == moma.MOMA_E_ARG
+    assert lib.moma_check_canonical(_w(q, L), L, 16, None, ctypes.byref(bad), None) == moma.MOMA_E_ARG
+    assert lib.moma_check_canonical(_w(q + 1, L), L, 16, DUMMY, ctypes.byref(bad), None) == moma.MOMA_E_MODULUS
+    assert lib.moma_check_canonical(_w(q, L), 1, 16, DUMMY, ctypes.byref(bad), None) == moma.MOMA_E_ARG
+    assert lib.moma_check_canonical(_w(q, L), L, 0, None, ctypes.byref(bad), None) == moma.MOMA_OK
+    assert bad.value == 0                                       # an empty vector has nothing to count
+    assert lib.moma_set_input_check(1) == moma.MOMA_OK and lib.moma_set_input_check(0) == moma.MOMA_OK
