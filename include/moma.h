@@ -101,6 +101,18 @@ int moma_check_canonical(const uint32_t* q, uint32_t limbs, uint64_t n, const ui
 int moma_set_input_check(int on);
 
 /*
+ * Layout conversion on the device, for data held as an array of multi-word
+ * integers (element i's limb j at d_elems[i * limbs + j], little-endian limbs).
+ *   moma_pack_planar:   d_planar[j * n + i] = d_elems[i * limbs + j]
+ *   moma_unpack_planar: d_elems[i * limbs + j] = d_planar[j * n + i]
+ * 2 <= limbs <= 32, n <= 2^31 (0 is a no-op).  Asynchronous on `stream`.  The
+ * two buffers must not overlap (the same pointer is MOMA_E_ARG).  Values are
+ * copied as words; no reduction mod q happens.
+ */
+int moma_pack_planar(uint32_t limbs, uint64_t n, const uint32_t* d_elems, uint32_t* d_planar, void* stream);
+int moma_unpack_planar(uint32_t limbs, uint64_t n, const uint32_t* d_planar, uint32_t* d_elems, void* stream);
+
+/*
  * Elementwise modular BLAS (paper Section 2.3; ring operations of Section 2.1).
  *   moma_vadd: out_i = (a_i + b_i) mod q
  *   moma_vsub: out_i = (a_i - b_i) mod q

@@ -70,6 +70,9 @@ _lib.moma_check_canonical.argtypes = [_u32p, ctypes.c_uint32, ctypes.c_uint64, _
 _lib.moma_check_canonical.restype = ctypes.c_int
 _lib.moma_set_input_check.argtypes = [ctypes.c_int]
 _lib.moma_set_input_check.restype = ctypes.c_int
+for _name in ("moma_pack_planar", "moma_unpack_planar"):
+    getattr(_lib, _name).argtypes = [ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp]
+    getattr(_lib, _name).restype = ctypes.c_int
 
 
 class Schedule(ctypes.Structure):
@@ -162,7 +165,8 @@ EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vad
             "moma_tune_db_get", "moma_tune_db_clear", "moma_tune_db_save", "moma_tune_db_load",
             "moma_costmodel_features", "moma_costmodel_train", "moma_costmodel_predict", "moma_costmodel_save",
             "moma_costmodel_load", "moma_costmodel_clear", "moma_mlp_nparams", "moma_mlp_forward", "moma_mlp_grad",
-            "moma_mlp_adam", "moma_check_canonical", "moma_set_input_check", "moma_shutdown")
+            "moma_mlp_adam", "moma_check_canonical", "moma_set_input_check", "moma_pack_planar",
+            "moma_unpack_planar", "moma_shutdown")
 
 
 class MomaError(RuntimeError):
@@ -276,6 +280,34 @@ def set_input_check(on: bool):
     """Debugging mode: every call first counts its non-canonical inputs and fails
     with MOMA_E_ARG if there are any (each such call waits for its stream)."""
     _check(_lib.moma_set_input_check(1 if on else 0))
+
+
+def pack(x, out=None, stream=None):
+    """Element-major (n, limbs) words -> the library's limb-planar (limbs, n)."""
+    _dev(x, "x")
+    n, limbs = x.shape
+    if out is None:
+        import torch
+        out = torch.empty((limbs, n), dtype=x.dtype, device=x.device)
+    _dev(out, "out")
+    if tuple(out.shape) != (limbs, n):
+        raise ValueError("out must have shape (limbs, n)")
+    _check(_lib.moma_pack_planar(limbs, n, x.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def unpack(x, out=None, stream=None):
+    """Limb-planar (limbs, n) -> element-major (n, limbs) words."""
+    _dev(x, "x")
+    limbs, n = x.shape
+    if out is None:
+        import torch
+        out = torch.empty((n, limbs), dtype=x.dtype, device=x.device)
+    _dev(out, "out")
+    if tuple(out.shape) != (n, limbs):
+        raise ValueError("out must have shape (n, limbs)")
+    _check(_lib.moma_unpack_planar(limbs, n, x.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
 
 
 def vmul_set_variant(q: int, limbs: int, variant: int):

@@ -382,4 +382,39 @@ int launch_count_noncanonical(const uint32_t* q, int ls, const uint32_t* d_x, ui
   return (int)hipGetLastError();
 }
 
+// Layout conversion between element-major words (element i's limb j at
+// i * L + j, the usual array of little-endian multi-word integers) and the
+// library's limb-planar layout (j * n + i).  A workgroup moves 256 elements
+// through LDS so that both the global reads and the global writes are
+// consecutive words; the LDS row stride is odd, so the column-wise LDS
+// accesses of one wavefront fall in distinct banks.
+__global__ __launch_bounds__(256) void layout_kernel(const u32* __restrict__ src, u32* __restrict__ dst, u64 n,
+                                                     u32 L, int to_planar) {
+  extern __shared__ u32 tile[];
+  const u32 S = L | 1u;
+  const u64 base = (u64)blockIdx.x * 256;
+  const u32 cnt = (u32)((n - base) < 256 ? (n - base) : 256);
+  const u32 tid = threadIdx.x;
+  if (to_planar) {
+    for (u32 k = tid; k < cnt * L; k += 256) tile[(k / L) * S + (k % L)] = src[base * L + k];
+    __syncthreads();
+    if (tid < cnt)
+      for (u32 j = 0; j < L; j++) dst[(u64)j * n + base + tid] = tile[tid * S + j];
+  } else {
+    if (tid < cnt)
+      for (u32 j = 0; j < L; j++) tile[tid * S + j] = src[(u64)j * n + base + tid];
+    __syncthreads();
+    for (u32 k = tid; k < cnt * L; k += 256) dst[base * L + k] = tile[(k / L) * S + (k % L)];
+  }
+}
+
+int launch_layout(const uint32_t* src, uint32_t* dst, uint64_t n, uint32_t L, bool to_planar, hipStream_t s) {
+  if (n == 0) return 0;
+  if (L < 1 || L > (uint32_t)kMaxLimbs) return (int)hipErrorInvalidValue;
+  const u64 blocks = (n + 255) / 256;
+  const size_t lds = (size_t)256 * (L | 1u) * sizeof(u32);
+  hipLaunchKernelGGL(layout_kernel, dim3((unsigned)blocks), dim3(256), lds, s, src, dst, n, L, to_planar ? 1 : 0);
+  return (int)hipGetLastError();
+}
+
 }  // namespace moma

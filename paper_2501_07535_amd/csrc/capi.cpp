@@ -762,6 +762,26 @@ int moma_check_canonical(const uint32_t* q, uint32_t limbs, uint64_t n, const ui
   return count_noncanonical(fe->f, d_x, n, (hipStream_t)stream, bad_out);
 }
 
+static int layout_entry(uint32_t limbs, uint64_t n, const uint32_t* d_src, uint32_t* d_dst, bool to_planar,
+                        void* stream) {
+  if (limbs < MOMA_MIN_LIMBS || limbs > MOMA_MAX_LIMBS) return set_error(MOMA_E_ARG, "limbs must be in [2, 32]");
+  if (n > (1ull << 31)) return set_error(MOMA_E_ARG, "n must be <= 2^31");
+  if (n == 0) return MOMA_OK;
+  if (!d_src || !d_dst) return set_error(MOMA_E_ARG, "device pointer is NULL");
+  if (d_src == d_dst) return set_error(MOMA_E_ARG, "layout conversion cannot run in place");
+  int e = launch_layout(d_src, d_dst, n, limbs, to_planar, (hipStream_t)stream);
+  if (e) return hip_fail(e, "layout launch");
+  return MOMA_OK;
+}
+
+int moma_pack_planar(uint32_t limbs, uint64_t n, const uint32_t* d_elems, uint32_t* d_planar, void* stream) {
+  return layout_entry(limbs, n, d_elems, d_planar, true, stream);
+}
+
+int moma_unpack_planar(uint32_t limbs, uint64_t n, const uint32_t* d_planar, uint32_t* d_elems, void* stream) {
+  return layout_entry(limbs, n, d_planar, d_elems, false, stream);
+}
+
 int moma_set_input_check(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_check_inputs = on ? 1 : 0;

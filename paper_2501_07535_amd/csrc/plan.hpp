@@ -87,6 +87,8 @@ int launch_fill_residues(uint32_t* p, uint64_t n, int planes, int top, uint32_t 
 // per-workgroup counts of the elements >= q over `ls` storage planes
 int launch_count_noncanonical(const uint32_t* q, int ls, const uint32_t* d_x, uint64_t n, uint32_t* d_partial,
                               uint32_t blocks, hipStream_t s);
+// element-major <-> limb-planar words (to_planar: src is element-major)
+int launch_layout(const uint32_t* src, uint32_t* dst, uint64_t n, uint32_t L, bool to_planar, hipStream_t s);
 // the input check of every entry point (MOMA_CHECK_INPUTS / moma_set_input_check)
 bool input_check_on();
 int count_noncanonical(const FieldRaw& f, const uint32_t* d_x, uint64_t n, hipStream_t s, uint64_t* bad);

@@ -178,3 +178,16 @@ def test_input_check_rejects_bad_arguments_on_the_host():
     assert lib.moma_check_canonical(_w(q, L), L, 0, None, ctypes.byref(bad), None) == moma.MOMA_OK
     assert bad.value == 0                                       # an empty vector has nothing to count
     assert lib.moma_set_input_check(1) == moma.MOMA_OK and lib.moma_set_input_check(0) == moma.MOMA_OK
+
+
+def test_layout_conversion_rejects_bad_arguments_on_the_host():
+    import paper_2501_07535_amd as moma
+    lib = moma.library()
+    other = ctypes.c_void_p(0x2000)
+    for fn in (lib.moma_pack_planar, lib.moma_unpack_planar):
+        assert fn(1, 16, DUMMY, other, None) == moma.MOMA_E_ARG             # limbs below 2
+        assert fn(33, 16, DUMMY, other, None) == moma.MOMA_E_ARG            # limbs above 32
+        assert fn(8, (1 << 31) + 1, DUMMY, other, None) == moma.MOMA_E_ARG
+        assert fn(8, 16, None, other, None) == moma.MOMA_E_ARG
+        assert fn(8, 16, DUMMY, DUMMY, None) == moma.MOMA_E_ARG             # in place
+        assert fn(8, 0, None, None, None) == moma.MOMA_OK                   # nothing to move
