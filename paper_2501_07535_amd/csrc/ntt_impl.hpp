@@ -175,6 +175,100 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
   }
 }
 
+// Exchange of a final-stage round: a <-> the partner lane's b, where the
+// partner of lane l is l ^ 32 (C = 32 groups per tile) or l ^ 16 (C = 16).
+// v_permlane32_swap / v_permlane16_swap swap the upper (odd) 32- (16-) lane
+// rows of the first operand with the lower (even) rows of the second.
+__device__ __forceinline__ void swap_with_partner(u32& a, u32& b, bool c32) {
+  if (c32) {
+    auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  }
+}
+
+// The pass's last R + 1 stages [sg0, k) without an LDS round trip before the
+// last one.  A radix-2^R round on stages sg0 .. k - 2 leaves element e of unit
+// v at row p0 + 2e of its block (p0 = block start + (v & 1)), so the partners
+// of the last stage, rows 2m and 2m + 1, sit in units v and v ^ 1: the same
+// group g, in lanes C apart of one wavefront (the units of a round are laid
+// out g-fastest).  Swapping the upper half of one unit's elements with the
+// lower half of its partner's puts both rows of a pair in one lane: lane half
+// h = v & 1 then holds pair j (elements j and j + 2^(R-1)) = rows
+// 2j + 2^R h and 2j + 2^R h + 1 of the block, whose last-stage block index is
+// 2^R lb + 2^(R-1) h + j.  Requires C in {16, 32}, whole wavefronts of units,
+// and a round that is not the transform's first.
+template <int L, int R, bool STORE>
+__device__ __forceinline__ void ntt_round_last(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
+                                               const NttC<L>& c) {
+  const u32* __restrict__ tw = a.tw;
+  const u32 k = t.k;
+  const u32 B = 1u << (k - sg0);        // block size (rows) at stage sg0: 2^(R+1)
+  const u32 units = (t.E >> R);
+  const bool c32 = t.logc == 5;
+  constexpr int H = 1 << (R - 1);
+  u32 q2v[L];
+  to_vgprs<L>(q2v, c.q2);
+  for (u32 b = threadIdx.x; b < units; b += blockDim.x) {
+    u32 g = b & (t.C - 1), v = b >> t.logc;
+    u32 lb = v >> 1;
+    u32 p0 = lb * B + (v & 1u);
+    u32 x[1 << R][L];
+#pragma unroll
+    for (int e = 0; e < (1 << R); e++)
+#pragma unroll
+      for (int j = 0; j < L; j++) x[e][j] = lds[(j * t.rows + p0 + 2 * e) * t.C + g];
+#pragma unroll
+    for (int s = 0; s < R; s++) {
+      const int kb = R - 1 - s, half = 1 << kb;
+#pragma unroll
+      for (int p = 0; p < (1 << (R - 1)); p++) {
+        const int e = ((p >> kb) << (kb + 1)) | (p & (half - 1));
+        u32 lbk = (lb << s) + (u32)(e >> (R - s));
+        u32 w[digit_stride(L)];
+        load_digits<L>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L));
+        ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < H; e++)
+#pragma unroll
+      for (int j = 0; j < L; j++) swap_with_partner(x[e][j], x[e + H][j], c32);
+    const u32 h = v & 1u;
+#pragma unroll
+    for (int jp = 0; jp < H; jp++) {
+      u32 lbk = (lb << R) + (h << (R - 1)) + (u32)jp;
+      u32 w[digit_stride(L)];
+      load_digits<L>(w, tw + tw_pos(t, k - 1, lbk, g) * digit_stride(L));
+      ct_butterfly_digits<L>(x[jp], x[jp + H], w, c.qd, c.qinvd, q2v);
+    }
+    const u32 r0 = lb * B + (h << R);
+    if constexpr (STORE) {
+      const u64 base = (t.ro << (t.K + k)) + t.b0 + g;
+#pragma unroll
+      for (int jp = 0; jp < H; jp++)
+#pragma unroll
+        for (int o = 0; o < 2; o++) {
+          u32* y = x[jp + o * H];
+          const u64 dst = base + ((u64)rev_bits(r0 + 2 * jp + o, k) << t.K);
+          finish_elem<L>(y, a, c);
+#pragma unroll
+          for (int j = 0; j < L; j++) a.out[(u64)j * t.n + dst] = y[j];
+        }
+    } else {
+#pragma unroll
+      for (int jp = 0; jp < H; jp++)
+#pragma unroll
+        for (int o = 0; o < 2; o++)
+#pragma unroll
+          for (int j = 0; j < L; j++) lds[(j * t.rows + r0 + 2 * jp + o) * t.C + g] = x[jp + o * H][j];
+    }
+  }
+}
 
 // One tile of one pass: stages [K, K+k) on C = 2^logc groups of 2^k elements.
 // LDS holds the tile limb-planar: word (j * 2^k + u) * C + g is limb j of row u
@@ -211,7 +305,9 @@ __device__ __forceinline__ void pointwise_digits(u32* r, const u32* x, const u32
 
 // MUL: the pass also multiplies its input by a.in2 element by element as it
 // loads (first pass of the inverse transform inside a cyclic product).
-template <int L, int R, bool MUL>
+// LASTX: the pass ends with ntt_round_last (radix-4 units only; the launcher
+// sets it when fused_last_applies holds, so other launches run unchanged code).
+template <int L, int R, bool MUL, bool LASTX = false>
 __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const NttC<L>& c, u64 tile) {
   TileGeo t;
   t.k = a.k;
@@ -332,6 +428,21 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
   u32 sg = 0;
   while (sg < t.k) {
     u32 rem = t.k - sg;
+    if constexpr (R == 2 && LASTX) {
+      // the last 3 stages with a cross-lane exchange before the last one
+      if (rem == 3u && (t.logc == 4 || t.logc == 5) && ((t.E >> 2) & 63u) == 0 && (t.E >> 2) >= blockDim.x &&
+          !(t.K == 0 && sg == 0)) {
+        if constexpr (kFuseStore<L>) {
+          if (fuse) {
+            ntt_round_last<L, R, true>(lds, t, sg, a, c);
+            return;
+          }
+        }
+        ntt_round_last<L, R, false>(lds, t, sg, a, c);
+        __syncthreads();
+        break;
+      }
+    }
     const u32 rr = rem < (u32)R ? rem : (u32)R;
     const bool store = fuse && sg + rr == t.k;
     if (rr == 4) {
@@ -426,10 +537,23 @@ struct PassTraits {
 };
 
 // One pass of one transform: workgroup b runs tile b.
-template <int L, int R, bool MUL>
+template <int L, int R, bool MUL, bool LASTX>
 __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a, NttC<L> c) {
   extern __shared__ u32 lds[];
-  pass_tile<L, R, MUL>(lds, a, c, blockIdx.x);
+  pass_tile<L, R, MUL, LASTX>(lds, a, c, blockIdx.x);
+}
+
+// Whether a pass with radix-4 units ends with ntt_round_last: its stage count
+// is odd (rounds 2, 2, ..., then 3), the tile has 16 or 32 groups, the units
+// fill whole wavefronts and every thread has one, and the fused round is not
+// the transform's first round.  Measured against the separate radix-2 round:
+// transforms 1 to 4% faster at 2^20 and 2^21 points from 64 to 256 bits; where
+// a thread would have no radix-4 unit the separate round, which keeps twice as
+// many threads busy, is faster.
+inline bool fused_last_applies(const NttPassArgs& a, uint32_t threads) {
+  if (a.k < 3 || (a.k & 1u) == 0 || (a.logc != 4 && a.logc != 5)) return false;
+  const uint64_t units = (1ull << (a.k + a.logc)) >> 2;
+  return units % 64 == 0 && units >= threads && !(a.K == 0 && a.k == 3);
 }
 
 // One phase of a batch: items[i] = (pass record, tile); every pass record names
@@ -504,23 +628,36 @@ inline NttC<L> make_consts(const FieldRaw& f, const DigitConsts& dc, const NttCo
   return c;
 }
 
-template <int L, int R, bool MUL>
+template <int L, int R, bool MUL, bool LASTX>
 int launch_pass_LRM(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
   size_t lds = (size_t)L * ((size_t)1 << (a.k + a.logc)) * sizeof(u32);
   static bool attr_set = false;
   if (lds > 65536 && !attr_set) {
-    (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R, MUL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+    (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R, MUL, LASTX>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL((ntt_pass_kernel<L, R, MUL>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
+  hipLaunchKernelGGL((ntt_pass_kernel<L, R, MUL, LASTX>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
   return (int)hipGetLastError();
+}
+
+// (up to 8 limbs: at 10 limbs the fused round measured level at 2^20 points
+// and 3% slower at 2^18)
+template <int L>
+constexpr bool kFusedLast = L <= 8;
+
+template <int L, int R, bool MUL>
+int launch_pass_LRX(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
+  if constexpr (R == 2 && kFusedLast<L>) {
+    if (fused_last_applies(a, threads)) return launch_pass_LRM<L, R, MUL, true>(c, a, threads, tiles, s);
+  }
+  return launch_pass_LRM<L, R, MUL, false>(c, a, threads, tiles, s);
 }
 
 template <int L, int R>
 int launch_pass_LR(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
-  return a.in2 ? launch_pass_LRM<L, R, true>(c, a, threads, tiles, s)
-               : launch_pass_LRM<L, R, false>(c, a, threads, tiles, s);
+  return a.in2 ? launch_pass_LRX<L, R, true>(c, a, threads, tiles, s)
+               : launch_pass_LRX<L, R, false>(c, a, threads, tiles, s);
 }
 
 template <int L>
