@@ -60,6 +60,7 @@ struct NttPassArgs {
   uint32_t logn, K, k, logc;
   uint32_t last;       // last pass: store canonical residues in [0, q)
   uint32_t scale;      // multiply by n^-1 on store (last pass of the inverse)
+  uint32_t direct;     // set by the pass launcher: the first round reads straight from `in`
 };
 
 // Launch shape of a transform: LDS tile of 2^tile_log elements, 2^col_log

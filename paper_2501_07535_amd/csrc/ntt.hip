@@ -6,6 +6,19 @@ namespace moma {
 
 MOMA_FOR_EACH_L(MOMA_NTT_EXTERN)
 
+// compute units of the current device (cached per device ordinal)
+uint32_t device_cu_count() {
+  static uint32_t cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cache[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cache[dev] = (uint32_t)v;
+  }
+  return cache[dev];
+}
+
 uint32_t ntt_max_threads(int L, uint32_t radix_log) {
   int live = L << radix_log;
   return live <= 16 ? 1024u : (live <= 32 ? 512u : 256u);

@@ -121,7 +121,10 @@ __device__ __forceinline__ void finish_elem(u32* x, const NttPassArgs& a, const 
   }
 }
 
-template <int L, int R, bool FIRST, bool STORE>
+// LOADG: the pass's first round reads its elements straight from the input in
+// HBM (the addresses the load phase would have filled the LDS rows from)
+// instead of from LDS, so the pass has no separate load phase.
+template <int L, int R, bool FIRST, bool STORE, bool LOADG = false>
 __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
                                           const NttC<L>& c) {
   const u32* __restrict__ tw = a.tw;
@@ -136,10 +139,21 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
     u32 lb = v >> (k - sg0 - R);
     u32 p0 = lb * B + (v & (sub - 1));
     u32 x[1 << R][L];
+    if constexpr (LOADG) {
 #pragma unroll
-    for (int e = 0; e < (1 << R); e++)
+      for (int e = 0; e < (1 << R); e++) {
+        const u32 u = p0 + e * sub;  // LDS row; global row u (first pass) or rev(u) (later passes)
+        const u64 src = (t.K == 0) ? (u64)u * t.S + t.o0 + g
+                                   : (t.ro << (t.K + k)) + ((u64)rev_bits(u, k) << t.K) + t.b0 + g;
 #pragma unroll
-      for (int j = 0; j < L; j++) x[e][j] = lds[(j * t.rows + p0 + e * sub) * t.C + g];
+        for (int j = 0; j < L; j++) x[e][j] = a.in[(u64)j * t.n + src];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < (1 << R); e++)
+#pragma unroll
+        for (int j = 0; j < L; j++) x[e][j] = lds[(j * t.rows + p0 + e * sub) * t.C + g];
+    }
 #pragma unroll
     for (int s = 0; s < R; s++) {
       const int kb = R - 1 - s, half = 1 << kb;
@@ -328,12 +342,16 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
   }
   const u32 tid = threadIdx.x, T = blockDim.x;
   const u64 n = t.n;
+  // LASTX passes without a fused product read their first round straight from HBM
+  const bool direct = LASTX && !MUL && a.direct != 0;
 
   // ---- load (natural order in the first pass, bit-reversed storage after).
   // Each lane moves 4 consecutive words per limb: 4 groups of one row when the
   // tile has C >= 4 groups, else 4 consecutive rows of a one-pass transform.
   const bool vec_g = t.C >= 4, vec_u = (t.C == 1 && t.S == 1 && t.rows >= 4);
-  if (vec_g || vec_u) {
+  if (direct) {
+    // the first round loads its own elements
+  } else if (vec_g || vec_u) {
     for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
       u32 e = e4 << 2;
       u32 g = e & (t.C - 1), v = e >> t.logc;
@@ -420,7 +438,7 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
       }
     }
   }
-  __syncthreads();
+  if (!direct) __syncthreads();
 
   // ---- stages, R at a time in registers
   // later passes with 16+ columns store from the last round's registers
@@ -428,6 +446,17 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
   u32 sg = 0;
   while (sg < t.k) {
     u32 rem = t.k - sg;
+    if constexpr (LASTX && !MUL) {
+      if (direct && sg == 0) {
+        if (t.K == 0)
+          ntt_round<L, R, true, false, true>(lds, t, 0, a, c);
+        else
+          ntt_round<L, R, false, false, true>(lds, t, 0, a, c);
+        sg = R;
+        __syncthreads();
+        continue;
+      }
+    }
     if constexpr (R == 2 && LASTX) {
       // the last 3 stages with a cross-lane exchange before the last one
       if (rem == 3u && (t.logc == 4 || t.logc == 5) && ((t.E >> 2) & 63u) == 0 && (t.E >> 2) >= blockDim.x &&
@@ -646,10 +675,27 @@ int launch_pass_LRM(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, ui
 template <int L>
 constexpr bool kFusedLast = L <= 8;
 
+// Whether a pass's first round reads its elements straight from HBM (the
+// LASTX variant does when it has no fused product): 16 or 32 groups per tile
+// (each load instruction then covers 64- or 128-byte runs, as the load phase's
+// do), more than one round, and at least two tiles per compute unit.  Measured:
+// 1 to 7% faster transforms from 64 to 256 bits at 2^19 to 2^25 points; with
+// one tile per compute unit (2^18 points, 256 bits) the load phase's wider
+// loads were 4% faster.
+uint32_t device_cu_count();
+inline bool direct_load_applies(const NttPassArgs& a, uint32_t radix_log, uint64_t tiles) {
+  return !a.in2 && (a.logc == 4 || a.logc == 5) && a.k > radix_log && tiles >= 2ull * device_cu_count();
+}
+
 template <int L, int R, bool MUL>
 int launch_pass_LRX(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
   if constexpr (R == 2 && kFusedLast<L>) {
-    if (fused_last_applies(a, threads)) return launch_pass_LRM<L, R, MUL, true>(c, a, threads, tiles, s);
+    const bool direct = direct_load_applies(a, R, tiles);
+    if (direct || fused_last_applies(a, threads)) {
+      NttPassArgs b = a;
+      b.direct = direct ? 1u : 0u;
+      return launch_pass_LRM<L, R, MUL, true>(c, b, threads, tiles, s);
+    }
   }
   return launch_pass_LRM<L, R, MUL, false>(c, a, threads, tiles, s);
 }
