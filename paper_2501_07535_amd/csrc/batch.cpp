@@ -31,7 +31,7 @@ namespace moma {
 
 struct BatchLaunch {
   int L;
-  bool mul;
+  bool mul, variant;
   uint32_t radix_log, threads, grid, nitems;
   size_t lds;
   const NttPassArgs* d_passes;
@@ -111,8 +111,9 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
   // whether the pass multiplies two inputs (first inverse pass of a cyclic
   // product: a kernel variant of its own), and the tile's LDS bytes (a launch
   // reserves its largest tile for every workgroup, so mixing sizes would cut
-  // the occupancy of the smaller tiles)
-  typedef std::tuple<int, uint32_t, uint32_t, bool, size_t> GKey;
+  // the occupancy of the smaller tiles), and whether the pass runs the kernel
+  // variant with the direct first round and the cross-lane last stage
+  typedef std::tuple<int, uint32_t, uint32_t, bool, size_t, bool> GKey;
   std::map<GKey, Group> groups;
   NttConsts none;
   memset(&none, 0, sizeof(none));
@@ -125,7 +126,6 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     for (size_t i = 0; i < passes.size(); i++) {
       const NttPass& ps = passes[i];
       const size_t tile_bytes = ((size_t)1 << (ps.k + ps.logc)) * f.L * sizeof(uint32_t);
-      Group& g = groups[GKey(f.L, sched.radix_log, sched.threads, i == 0 && in2 != nullptr, tile_bytes)];
       NttPassArgs a{};
       a.in = (i == 0) ? in : (i == 1 ? first_out : out);
       a.in2 = (i == 0) ? in2 : nullptr;
@@ -138,6 +138,8 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       a.logc = ps.logc;
       a.last = (i + 1 == passes.size()) ? 1u : 0u;
       a.scale = (scale && i + 1 == passes.size()) ? 1u : 0u;
+      const bool variant = ntt_batch_variant(f.L, sched.radix_log, sched.threads, &a);
+      Group& g = groups[GKey(f.L, sched.radix_log, sched.threads, i == 0 && in2 != nullptr, tile_bytes, variant)];
       uint32_t rec = (uint32_t)g.recs.size();
       g.recs.push_back(a);
       size_t off = g.consts.size();
@@ -313,6 +315,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       BatchLaunch bl;
       bl.L = L;
       bl.mul = std::get<3>(kv.first);
+      bl.variant = std::get<5>(kv.first);
       bl.radix_log = std::get<1>(kv.first);
       bl.threads = std::get<2>(kv.first);
       bl.lds = kv.second.lds[ph];
@@ -365,7 +368,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     }
   for (const BatchLaunch& bl : b.launches) {
     if (err) break;
-    err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.threads, bl.lds, bl.grid, bl.d_passes, bl.d_consts,
+    err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.variant, bl.threads, bl.lds, bl.grid, bl.d_passes, bl.d_consts,
                            bl.d_items, bl.nitems, b.cap);
     if (err) break;
   }

@@ -97,9 +97,12 @@ int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs&
 size_t ntt_consts_bytes(int L);
 void ntt_batch_prepare(int L, uint32_t radix_log, size_t lds);
 void ntt_fill_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc, void* dst);
-int launch_ntt_batch(int L, uint32_t radix_log, bool mul, uint32_t threads, size_t lds, uint32_t grid,
+int launch_ntt_batch(int L, uint32_t radix_log, bool mul, bool variant, uint32_t threads, size_t lds, uint32_t grid,
                      const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
                      hipStream_t s);
+// whether a batch pass record runs the variant kernel (direct first round,
+// cross-lane last stage); sets the record's `direct` flag
+bool ntt_batch_variant(int L, uint32_t radix_log, uint32_t threads, NttPassArgs* a);
 // largest workgroup the pass kernel for (L, radix_log) was compiled for
 uint32_t ntt_max_threads(int L, uint32_t radix_log);
 int launch_twiddle_gen(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t n, uint32_t logn,

@@ -35,12 +35,17 @@ int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs&
   return (int)hipErrorInvalidValue;
 }
 
-int launch_ntt_batch(int L, uint32_t radix_log, bool mul, uint32_t threads, size_t lds, uint32_t grid,
+bool ntt_batch_variant(int L, uint32_t radix_log, uint32_t threads, NttPassArgs* a) {
+  return batch_variant(L, radix_log, threads, a);
+}
+
+int launch_ntt_batch(int L, uint32_t radix_log, bool mul, bool variant, uint32_t threads, size_t lds, uint32_t grid,
                      const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
                      hipStream_t s) {
   switch (L) {
-#define CASE(LL) \
-  case LL: return launch_batch_L<LL>(radix_log, mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+#define CASE(LL)                                                                                                  \
+  case LL:                                                                                                        \
+    return launch_batch_L<LL>(radix_log, mul, variant, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }

@@ -589,7 +589,7 @@ inline bool fused_last_applies(const NttPassArgs& a, uint32_t threads) {
 // its own transform (buffers, size, stages, twiddles) and its modulus constants.
 // Workgroup i runs item i; items are sorted by decreasing cost, so the
 // dispatcher hands out the largest tiles first.
-template <int L, int R, bool MUL>
+template <int L, int R, bool MUL, bool LASTX>
 __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_kernel(
     const NttPassArgs* __restrict__ passes, const NttC<L>* __restrict__ consts, const uint2* __restrict__ items,
     u32 nitems) {
@@ -599,7 +599,7 @@ __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_ker
   const uint2 it = items[i];
   const NttPassArgs a = passes[it.x];
   const NttC<L> c = consts[it.x];
-  pass_tile<L, R, MUL>(lds, a, c, it.y);
+  pass_tile<L, R, MUL, LASTX>(lds, a, c, it.y);
 }
 
 // Twiddle table: entry e = 2^s + i' holds w^(i' * 2^(logn-s-1)) * 2^(32L) mod q.
@@ -687,6 +687,16 @@ inline bool direct_load_applies(const NttPassArgs& a, uint32_t radix_log, uint64
   return !a.in2 && (a.logc == 4 || a.logc == 5) && a.k > radix_log && tiles >= 2ull * device_cu_count();
 }
 
+// The batch executor's choice for one pass record: the variant kernel when the
+// pass would take the cross-lane last stage or the direct first round (a batch
+// launch holds many tiles, so the tile-count rule of a lone call is not applied).
+inline bool batch_variant(int L, uint32_t radix_log, uint32_t threads, NttPassArgs* a) {
+  if (radix_log != 2 || L > 8) return false;
+  const bool direct = !a->in2 && (a->logc == 4 || a->logc == 5) && a->k > radix_log;
+  a->direct = direct ? 1u : 0u;
+  return direct || fused_last_applies(*a, threads);
+}
+
 template <int L, int R, bool MUL>
 int launch_pass_LRX(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
   if constexpr (R == 2 && kFusedLast<L>) {
@@ -724,34 +734,46 @@ int launch_pass_L(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a
   return (int)hipErrorInvalidValue;
 }
 
-template <int L, int R>
-int launch_batch_LR(bool mul, uint32_t threads, size_t lds, uint32_t grid, const NttPassArgs* d_passes,
-                    const void* d_consts, const uint2* d_items, uint32_t nitems, hipStream_t s) {
+template <int L, int R, bool LASTX>
+int launch_batch_LRX(bool mul, uint32_t threads, size_t lds, uint32_t grid, const NttPassArgs* d_passes,
+                     const void* d_consts, const uint2* d_items, uint32_t nitems, hipStream_t s) {
   if (mul)
-    hipLaunchKernelGGL((ntt_batch_kernel<L, R, true>), dim3(grid), dim3(threads), lds, s, d_passes,
+    hipLaunchKernelGGL((ntt_batch_kernel<L, R, true, LASTX>), dim3(grid), dim3(threads), lds, s, d_passes,
                        (const NttC<L>*)d_consts, d_items, nitems);
   else
-    hipLaunchKernelGGL((ntt_batch_kernel<L, R, false>), dim3(grid), dim3(threads), lds, s, d_passes,
+    hipLaunchKernelGGL((ntt_batch_kernel<L, R, false, LASTX>), dim3(grid), dim3(threads), lds, s, d_passes,
                        (const NttC<L>*)d_consts, d_items, nitems);
   return (int)hipGetLastError();
 }
 
+template <int L, int R>
+int launch_batch_LR(bool mul, bool lastx, uint32_t threads, size_t lds, uint32_t grid, const NttPassArgs* d_passes,
+                    const void* d_consts, const uint2* d_items, uint32_t nitems, hipStream_t s) {
+  if constexpr (R == 2 && kFusedLast<L>) {
+    if (lastx)
+      return launch_batch_LRX<L, R, true>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  }
+  if (lastx) return (int)hipErrorInvalidValue;
+  return launch_batch_LRX<L, R, false>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+}
+
 template <int L>
-int launch_batch_L(uint32_t radix_log, bool mul, uint32_t threads, size_t lds, uint32_t grid,
+int launch_batch_L(uint32_t radix_log, bool mul, bool lastx, uint32_t threads, size_t lds, uint32_t grid,
                    const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
                    hipStream_t s) {
-  if (radix_log == 1) return launch_batch_LR<L, 1>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+  if (radix_log == 1)
+    return launch_batch_LR<L, 1>(mul, lastx, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
   if constexpr (L <= kMaxLimbsRadix4) {
     if (radix_log == 2)
-      return launch_batch_LR<L, 2>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+      return launch_batch_LR<L, 2>(mul, lastx, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
   }
   if constexpr (L <= kMaxLimbsRadix8) {
     if (radix_log == 3)
-      return launch_batch_LR<L, 3>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+      return launch_batch_LR<L, 3>(mul, lastx, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
   }
   if constexpr (L <= kMaxLimbsRadix16) {
     if (radix_log == 4)
-      return launch_batch_LR<L, 4>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+      return launch_batch_LR<L, 4>(mul, lastx, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
   }
   return (int)hipErrorInvalidValue;
 }
@@ -760,10 +782,16 @@ int launch_batch_L(uint32_t radix_log, bool mul, uint32_t threads, size_t lds, u
 // capture so that nothing but launches is recorded
 template <int L, int R>
 void batch_attr_LR() {
-  (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-  (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, false, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, true, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if constexpr (R == 2 && kFusedLast<L>) {
+    (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, true, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  }
 }
 
 template <int L>
@@ -797,7 +825,7 @@ int launch_tw_L(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t
 #define MOMA_NTT_DECLARE(PREFIX, LL)                                                                              \
   PREFIX template int launch_pass_L<LL>(const FieldRaw&, const DigitConsts&, const NttPassArgs&, const NttConsts&, \
                                         uint32_t, uint64_t, uint32_t, hipStream_t);                                 \
-  PREFIX template int launch_batch_L<LL>(uint32_t, bool, uint32_t, size_t, uint32_t, const NttPassArgs*,           \
+  PREFIX template int launch_batch_L<LL>(uint32_t, bool, bool, uint32_t, size_t, uint32_t, const NttPassArgs*,     \
                                          const void*, const uint2*, uint32_t, hipStream_t);                         \
   PREFIX template void batch_attr_L<LL>(uint32_t);                                                                  \
   PREFIX template int launch_tw_L<LL>(const FieldRaw&, const DigitConsts&, uint32_t*, uint64_t, uint32_t,          \
