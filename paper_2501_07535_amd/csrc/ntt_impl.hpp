@@ -457,10 +457,10 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
         continue;
       }
     }
-    if constexpr (R == 2 && LASTX) {
-      // the last 3 stages with a cross-lane exchange before the last one
-      if (rem == 3u && (t.logc == 4 || t.logc == 5) && ((t.E >> 2) & 63u) == 0 && (t.E >> 2) >= blockDim.x &&
-          !(t.K == 0 && sg == 0)) {
+    if constexpr ((R == 2 || R == 3) && LASTX) {
+      // the last R + 1 stages with a cross-lane exchange before the last one
+      if (rem == (u32)R + 1 && (t.logc == 4 || t.logc == 5) && ((t.E >> R) & 63u) == 0 &&
+          (t.E >> R) >= blockDim.x && !(t.K == 0 && sg == 0)) {
         if constexpr (kFuseStore<L>) {
           if (fuse) {
             ntt_round_last<L, R, true>(lds, t, sg, a, c);
@@ -579,10 +579,11 @@ __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kern
 // transforms 1 to 4% faster at 2^20 and 2^21 points from 64 to 256 bits; where
 // a thread would have no radix-4 unit the separate round, which keeps twice as
 // many threads busy, is faster.
-inline bool fused_last_applies(const NttPassArgs& a, uint32_t threads) {
-  if (a.k < 3 || (a.k & 1u) == 0 || (a.logc != 4 && a.logc != 5)) return false;
-  const uint64_t units = (1ull << (a.k + a.logc)) >> 2;
-  return units % 64 == 0 && units >= threads && !(a.K == 0 && a.k == 3);
+inline bool fused_last_applies(const NttPassArgs& a, uint32_t threads, uint32_t radix_log) {
+  const uint32_t r = radix_log;
+  if (a.k < r + 1 || (a.k - r - 1) % r != 0 || (a.logc != 4 && a.logc != 5)) return false;
+  const uint64_t units = (1ull << (a.k + a.logc)) >> r;
+  return units % 64 == 0 && units >= threads && !(a.K == 0 && a.k == r + 1);
 }
 
 // One phase of a batch: items[i] = (pass record, tile); every pass record names
@@ -691,17 +692,17 @@ inline bool direct_load_applies(const NttPassArgs& a, uint32_t radix_log, uint64
 // pass would take the cross-lane last stage or the direct first round (a batch
 // launch holds many tiles, so the tile-count rule of a lone call is not applied).
 inline bool batch_variant(int L, uint32_t radix_log, uint32_t threads, NttPassArgs* a) {
-  if (radix_log != 2 || L > 8) return false;
+  if ((radix_log != 2 && radix_log != 3) || L > 8) return false;
   const bool direct = !a->in2 && (a->logc == 4 || a->logc == 5) && a->k > radix_log;
   a->direct = direct ? 1u : 0u;
-  return direct || fused_last_applies(*a, threads);
+  return direct || fused_last_applies(*a, threads, radix_log);
 }
 
 template <int L, int R, bool MUL>
 int launch_pass_LRX(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
-  if constexpr (R == 2 && kFusedLast<L>) {
+  if constexpr ((R == 2 || R == 3) && kFusedLast<L>) {
     const bool direct = direct_load_applies(a, R, tiles);
-    if (direct || fused_last_applies(a, threads)) {
+    if (direct || fused_last_applies(a, threads, R)) {
       NttPassArgs b = a;
       b.direct = direct ? 1u : 0u;
       return launch_pass_LRM<L, R, MUL, true>(c, b, threads, tiles, s);
@@ -749,7 +750,7 @@ int launch_batch_LRX(bool mul, uint32_t threads, size_t lds, uint32_t grid, cons
 template <int L, int R>
 int launch_batch_LR(bool mul, bool lastx, uint32_t threads, size_t lds, uint32_t grid, const NttPassArgs* d_passes,
                     const void* d_consts, const uint2* d_items, uint32_t nitems, hipStream_t s) {
-  if constexpr (R == 2 && kFusedLast<L>) {
+  if constexpr ((R == 2 || R == 3) && kFusedLast<L>) {
     if (lastx)
       return launch_batch_LRX<L, R, true>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
   }
@@ -786,7 +787,7 @@ void batch_attr_LR() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, true, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if constexpr (R == 2 && kFusedLast<L>) {
+  if constexpr ((R == 2 || R == 3) && kFusedLast<L>) {
     (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, false, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipFuncSetAttribute((const void*)ntt_batch_kernel<L, R, true, true>,

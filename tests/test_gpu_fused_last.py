@@ -1,7 +1,8 @@
 """Passes whose last three stages run as one radix-4 round plus a final stage
 whose partners are exchanged across lanes (v_permlane32_swap / 16_swap), not
-through LDS: transforms, inverses and cyclic products in launch shapes that
-take that path (first pass and later passes, 16 and 32 groups per tile, 2 to 8
+through LDS, and whose first round reads straight from HBM: transforms,
+inverses and cyclic products in launch shapes that take those paths (first and
+later passes, 16 and 32 groups per tile, radix-4 and radix-8 units, 2 to 8
 limbs) equal the oracle's."""
 import pytest
 
@@ -11,7 +12,9 @@ from gpu_util import from_dev, say, to_dev
 pytestmark = pytest.mark.gpu
 
 CASES = [(256, 15, (10, 5, 256, 2)), (256, 13, (9, 4, 128, 2)), (64, 15, (9, 4, 128, 2)),
-         (160, 17, (10, 5, 256, 2)), (256, 14, (11, 4, 256, 2)), (128, 15, (10, 5, 128, 2))]
+         (160, 17, (10, 5, 256, 2)), (256, 14, (11, 4, 256, 2)), (128, 15, (10, 5, 128, 2)),
+         # radix-8 units: last 4 stages fused (k = 7) and the direct first round
+         (128, 14, (11, 4, 256, 3)), (64, 14, (11, 4, 256, 3)), (160, 19, (11, 5, 256, 3))]
 
 
 @pytest.mark.parametrize("lam,logn,sched", CASES)
