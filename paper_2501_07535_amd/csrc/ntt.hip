@@ -1,22 +1,27 @@
 // ntt.hip - run-time dispatch of the transform kernels on the compute limb
 // count; the kernels and their launchers are in ntt_impl.hpp.
+#include <atomic>
+
 #include "ntt_impl.hpp"
 
 namespace moma {
 
 MOMA_FOR_EACH_L(MOMA_NTT_EXTERN)
 
-// compute units of the current device (cached per device ordinal)
+// compute units of the current device (cached per device ordinal; several
+// host threads may ask at once)
 uint32_t device_cu_count() {
-  static uint32_t cache[64] = {0};
+  static std::atomic<uint32_t> cache[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!cache[dev]) {
+  uint32_t c = cache[dev].load(std::memory_order_relaxed);
+  if (!c) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
-    cache[dev] = (uint32_t)v;
+    c = (uint32_t)v;
+    cache[dev].store(c, std::memory_order_relaxed);
   }
-  return cache[dev];
+  return c;
 }
 
 uint32_t ntt_max_threads(int L, uint32_t radix_log) {

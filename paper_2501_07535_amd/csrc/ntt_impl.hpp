@@ -31,6 +31,8 @@
 #pragma once
 #include <string.h>
 
+#include <atomic>
+
 #include "common.hpp"
 #include "limb.hpp"
 
@@ -661,11 +663,11 @@ inline NttC<L> make_consts(const FieldRaw& f, const DigitConsts& dc, const NttCo
 template <int L, int R, bool MUL, bool LASTX>
 int launch_pass_LRM(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
   size_t lds = (size_t)L * ((size_t)1 << (a.k + a.logc)) * sizeof(u32);
-  static bool attr_set = false;
-  if (lds > 65536 && !attr_set) {
+  static std::atomic<bool> attr_set{false};  // several host threads may launch at once
+  if (lds > 65536 && !attr_set.load(std::memory_order_acquire)) {
     (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R, MUL, LASTX>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
+    attr_set.store(true, std::memory_order_release);
   }
   hipLaunchKernelGGL((ntt_pass_kernel<L, R, MUL, LASTX>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
   return (int)hipGetLastError();
