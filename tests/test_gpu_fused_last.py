@@ -49,3 +49,38 @@ def test_fused_last_stage_in_the_cyclic_product():
     say("fused last stage cyclic product")
     assert (from_dev(moma.ntt_cyclic_mul(to_dev(a), to_dev(b), q, w)) == want).all()
     moma.ntt_set_schedule(q, w, n, L, None)
+
+
+def test_variant_passes_inside_a_batch():
+    """Batch jobs whose passes take the variant (odd stage counts with 16 or 32
+    groups under the batch's own launch shapes): forward, inverse and cyclic
+    products equal the oracle."""
+    import torch
+
+    import oracle
+    import paper_2501_07535_amd as moma
+    specs, checks, keep = [], [], []
+    for lam, logn, kind in ((256, 15, moma.JOB_FORWARD), (256, 15, moma.JOB_CYCLIC_MUL), (128, 14, moma.JOB_INVERSE),
+                            (128, 14, moma.JOB_CYCLIC_MUL), (64, 17, moma.JOB_FORWARD), (160, 13, moma.JOB_CYCLIC_MUL)):
+        f = mi.find_prime(lam, 2)
+        L, n, q = f.limbs, 1 << logn, f.q
+        w = f.root(n)
+        a, b = mi.residues(f, n, L, 732, logn, 1), mi.residues(f, n, L, 732, logn, 2)
+        da, db = to_dev(a), to_dev(b)
+        o = torch.empty_like(da)
+        keep += [da, db]
+        specs.append(((da, db) if kind == moma.JOB_CYCLIC_MUL else da, o, q, w, kind))
+        if kind == moma.JOB_FORWARD:
+            want = oracle.ntt_radix2(q, L, w, a)
+        elif kind == moma.JOB_INVERSE:
+            want = oracle.intt_radix2(q, L, w, a)
+        else:
+            want = oracle.intt_radix2(q, L, w, oracle.vmul(q, L, oracle.ntt_radix2(q, L, w, a), oracle.ntt_radix2(q, L, w, b)))
+        checks.append((o, want, lam, logn, kind))
+    say("variant passes in a batch")
+    bt = moma.Batch(specs)
+    bt.run()
+    torch.cuda.synchronize()
+    for o, want, lam, logn, kind in checks:
+        assert (from_dev(o) == want).all(), (lam, logn, kind)
+    bt.close()
