@@ -32,7 +32,7 @@ __device__ __forceinline__ void load_words(u32* w, const u32* __restrict__ p) {
     uint2 t = *reinterpret_cast<const uint2*>(p);
     w[0] = t.x; w[1] = t.y;
   } else {
-    w[0] = p[0];
+    w[0] = __builtin_nontemporal_load(p);  // streamed once: no reuse to keep in the caches
   }
 }
 
@@ -43,7 +43,7 @@ __device__ __forceinline__ void store_words(u32* __restrict__ p, const u32* w) {
   } else if constexpr (V == 2) {
     *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
   } else {
-    p[0] = w[0];
+    __builtin_nontemporal_store(w[0], p);
   }
 }
 
