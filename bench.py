@@ -149,8 +149,16 @@ def blas(args):
         # vmul: the autotuner picks schoolbook or Karatsuba products for this width
         tuned = moma.vmul_tune(q, L, n, reps=5)
         for op, fn in calls.items():
-            for _ in range(args.warmup):
+            # warm up for at least ~0.2 s of this op: the clock settles to the
+            # op's own power draw (a few calls right after a memory-bound op
+            # time the multiply-heavy ones up to 15% slow)
+            t0 = time.time()
+            k = 0
+            while k < args.warmup or time.time() - t0 < 0.2:
                 fn()
+                k += 1
+                if k % 16 == 0:
+                    torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             e0.record(stream)
