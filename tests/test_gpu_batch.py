@@ -111,3 +111,34 @@ def test_batch_blas_jobs_with_transforms():
         bt.close()
     finally:
         moma.vmul_set_variant(f8.q, 8, moma.VMUL_SCHOOLBOOK)
+
+
+def test_batch_4096_job_workload_sampled_against_oracle():
+    """The benchmarked workload itself (4096 forward transforms, 64..384 bits,
+    2^10..2^16 points, a prime each, one graph launch): 64 seeded jobs, 16 of
+    each width, compared element by element with the oracle's transform; every
+    job equal to its plain call."""
+    import oracle
+    import paper_2501_07535_amd as moma
+    jobs = mi.batch_jobs(4096)
+    xs = mi.batch_inputs(jobs)
+    dx = [to_dev(x) for x in xs]
+    outs = [torch.empty_like(x) for x in dx]
+    say("batch create 4096 jobs (the benchmarked workload)")
+    b = moma.Batch([(x, o, j.field.q, j.omega, False) for j, x, o in zip(jobs, dx, outs)])
+    b.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4096)
+    picks = []
+    for lam in mi.BATCH_WIDTHS:
+        idx = [j.index for j in jobs if j.lam == lam]
+        picks += list(rng.choice(idx, size=16, replace=False))
+    say(f"batch 4096: oracle check of {len(picks)} jobs")
+    for k in picks:
+        j = jobs[k]
+        want = oracle.ntt_radix2(j.field.q, j.limbs, j.omega, xs[k])
+        assert (from_dev(outs[k]) == want).all(), (k, j.lam, j.logn)
+    say("batch 4096: every job against its plain call")
+    for j, x, o in zip(jobs, dx, outs):
+        assert torch.equal(moma.ntt_fwd(x, j.field.q, j.omega), o), (j.index, j.lam, j.logn)
+    b.close()

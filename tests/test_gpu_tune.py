@@ -110,3 +110,65 @@ def test_tuners_with_storage_wider_than_the_modulus():
     assert (from_dev(moma.vmul(to_dev(a), to_dev(b), q)) == oracle.vmul(q, Ls, a, b)).all()
     moma.vmul_set_variant(q, Ls, moma.VMUL_SCHOOLBOOK)
     moma.ntt_set_schedule(q, w, n, Ls, None)
+
+
+def _random_k_expected(times, k):
+    """Expected best time of k distinct candidates drawn uniformly at random:
+    the i-th fastest (0-based) is the best of the draw with probability
+    C(N-1-i, k-1) / C(N, k)."""
+    from math import comb
+    t = sorted(times)
+    N = len(t)
+    return sum(t[i] * comb(N - 1 - i, k - 1) for i in range(N)) / comb(N, k)
+
+
+def test_learned_model_gains_over_default_rule_and_random_picks():
+    """What the trained network gains over the method without it.  Sixteen
+    shapes (4 widths x 4 sizes) are tuned exhaustively; a fresh network is
+    trained on the GPU from twelve of them; on the four held-out shapes,
+    timing only the network's top 3 candidates must cost less (geometric mean
+    regret against the exhaustive best) than the fixed default rule and than
+    3 random candidates."""
+    import paper_2501_07535_amd as moma
+    widths, sizes = (64, 128, 256, 384), (10, 12, 14, 16)
+    held = {(128, 12), (256, 14), (64, 14), (384, 12)}
+    moma.tune_db_clear()
+    shapes = {}
+    try:
+        for lam in widths:
+            f = mi.find_prime(lam, 0)
+            for logn in sizes:
+                n = 1 << logn
+                say(f"gain test: tune {lam}-bit 2^{logn}")
+                moma.ntt_tune(f.q, f.root(n), n, f.limbs, reps=3, warmup=1)
+                shapes[(lam, logn)] = f.limbs
+        rows = moma.tune_db_rows()
+        by_shape = {}
+        for r in rows:
+            by_shape.setdefault((r["limbs"], r["log2_n"]), {})[tuple(r["sched"])] = r["us"]
+        train = [r for r in rows if (32 * r["limbs"], r["log2_n"]) not in held]
+        feats = np.array([moma.costmodel_features(r["limbs"], r["log2_n"], r["sched"]) for r in train], np.float32)
+        y = np.log(np.array([r["us"] for r in train], np.float32))
+        say(f"gain test: train on {len(train)} timings")
+        moma.costmodel_train(feats, y, epochs=300, batch=128, lr=3e-3, seed=11)
+        model, default, rand3 = [], [], []
+        for lam, logn in sorted(held):
+            L = shapes[(lam, logn)]
+            t = by_shape[(L, logn)]
+            cands = list(t)
+            best = min(t.values())
+            pf = np.array([moma.costmodel_features(L, logn, s) for s in cands], np.float32)
+            order = np.argsort(moma.costmodel_predict(pf), kind="stable")
+            model.append(min(t[cands[i]] for i in order[:3]) / best)
+            default.append(t[tuple(moma.ntt_default_schedule(L, logn))] / best)
+            rand3.append(_random_k_expected(list(t.values()), 3) / best)
+        g = {name: float(np.exp(np.mean(np.log(v)))) - 1 for name, v in
+             (("model_top3", model), ("default_rule", default), ("random_3", rand3))}
+        say(f"gain test: held-out geomean regret {g}; per shape model {model} default {default} random {rand3}")
+        assert g["model_top3"] < g["random_3"]
+        assert g["model_top3"] <= g["default_rule"]
+    finally:
+        moma.tune_db_clear()
+        moma.costmodel_clear()
+        moma.load_packaged_costmodel()
+        moma.shutdown()
