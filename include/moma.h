@@ -100,6 +100,7 @@ int moma_check_canonical(const uint32_t* q, uint32_t limbs, uint64_t n, const ui
                          void* stream);
 int moma_set_input_check(int on);
 
+
 /*
  * Layout conversion on the device, for data held as an array of multi-word
  * integers (element i's limb j at d_elems[i * limbs + j], little-endian limbs).
@@ -382,6 +383,34 @@ int moma_batch_run(moma_batch_t batch, void* stream);
 int moma_batch_info(moma_batch_t batch, uint32_t* launches, uint64_t* items);
 /* Release the graph and the batch's tables (plans stay cached). */
 int moma_batch_destroy(moma_batch_t batch);
+
+/*
+ * Measured issue rates and bandwidths (measurement support, not a step of the
+ * method).  The roofline of the integer kernels prices a modular multiply as
+ * its word products and carry steps (Section 2.2: a 2w-bit product from
+ * w-bit products, additions with carry); on gfx950 a word product with its
+ * 64-bit accumulation is one v_mad_u64_u32 and a carry step one
+ * v_addc_co_u32.  moma_measure_peaks times long runs of independent chains of
+ * each instruction over every SIMD of the device (latency hidden, only issue
+ * throughput counts) and two streaming kernels over buffers of hbm_bytes
+ * each (0 means 1 GiB; at most 16 GiB): rates in lane operations per second
+ * (for add_co_addc_u32 and mad_addc_u32 both instructions of a pair count)
+ * and bytes per second (read plus written).  Allocates three buffers of
+ * hbm_bytes for the duration of the call and synchronises `stream`.  Errors:
+ * MOMA_E_ARG (NULL out, hbm_bytes out of range), MOMA_E_NOMEM, MOMA_E_HIP.
+ */
+typedef struct moma_peak_rates {
+  double add_u32;          /* v_add_u32: the full-rate reference */
+  double add_co_addc_u32;  /* v_add_co_u32 followed by v_addc_co_u32 */
+  double mad_u64_u32;      /* v_mad_u64_u32: 32x32-bit product plus 64-bit addend */
+  double mad_addc_u32;     /* v_mad_u64_u32 whose carry-out feeds a v_addc_co_u32 */
+  double mul_lo_u32;       /* v_mul_lo_u32 */
+  double mul_hi_u32;       /* v_mul_hi_u32 */
+  double hbm_copy;         /* one read per write, bytes/s */
+  double hbm_triad;        /* two reads per write, bytes/s */
+  uint32_t compute_units;
+} moma_peak_rates_t;
+int moma_measure_peaks(moma_peak_rates_t* out, uint64_t hbm_bytes, void* stream);
 
 /* Free every cached plan and device table.  Safe to call more than once. */
 void moma_shutdown(void);

@@ -19,19 +19,24 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "moma_oracle.c")
-_LIB = os.path.join(_HERE, "libmoma_oracle.so")
+# MOMA_ORACLE_LIB names another build of the same source (the test suite runs
+# the pins once more against a build with memory and undefined-behaviour checks)
+_LIB = os.environ.get("MOMA_ORACLE_LIB") or os.path.join(_HERE, "libmoma_oracle.so")
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc and OpenMP (in place, next to its source)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, out: str | None = None, flags: list[str] | None = None) -> str:
+    """Compile the oracle with gcc and OpenMP (in place, next to its source, or
+    to `out`; `flags` replaces the default -O2)."""
+    path = out or _LIB
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
+        opt = list(flags) if flags else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
 
 
 _lib = None

@@ -21,112 +21,46 @@ struct BlasC {
   u32 ls;
 };
 
-// V consecutive words of one limb plane in one load or store (16-byte or
-// 8-byte accesses: fewer memory instructions per byte than one word per lane)
-template <int V>
-__device__ __forceinline__ void load_words(u32* w, const u32* __restrict__ p) {
-  if constexpr (V == 4) {
-    uint4 t = *reinterpret_cast<const uint4*>(p);
-    w[0] = t.x; w[1] = t.y; w[2] = t.z; w[3] = t.w;
-  } else if constexpr (V == 2) {
-    uint2 t = *reinterpret_cast<const uint2*>(p);
-    w[0] = t.x; w[1] = t.y;
-  } else {
-    w[0] = __builtin_nontemporal_load(p);  // streamed once: no reuse to keep in the caches
-  }
-}
-
-template <int V>
-__device__ __forceinline__ void store_words(u32* __restrict__ p, const u32* w) {
-  if constexpr (V == 4) {
-    *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
-  } else if constexpr (V == 2) {
-    *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
-  } else {
-    __builtin_nontemporal_store(w[0], p);
-  }
-}
-
-// Each lane handles V consecutive elements (n a multiple of V, planes aligned
-// to 4V bytes; the host falls back to V = 1 otherwise).
-template <int L, int OP, bool KARA, int V>
+// One element per lane.  Every word is streamed once, so loads and stores are
+// nontemporal (no reuse to keep in the caches).  Four elements per lane with
+// 16-byte accesses was measured at n = 2^24: vadd at 256 bits took 333 us
+// against 280 us with one element per lane.
+template <int L, int OP, bool KARA>
 __global__ __launch_bounds__(256) void blas_kernel(const u32* __restrict__ pa, const u32* __restrict__ pb,
                                                    u32* __restrict__ pout, u64 n, BlasC<L> c) {
-  u64 i = ((u64)blockIdx.x * blockDim.x + threadIdx.x) * V;
+  const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   // a full-width modulus has one storage plane fewer than compute limbs: the
   // missing top limb of every input is zero, and the result's is zero too
   const int lim = c.ls < (u32)L ? (int)c.ls : L;
-  u32 a[V][L], b[V][L];
+  u32 a[L], b[L], r[L];
 #pragma unroll
   for (int j = 0; j < L; j++) {
-    u32 wa[V], wb[V];
-    if (j < lim) {
-      load_words<V>(wa, pa + (u64)j * n + i);
-      load_words<V>(wb, pb + (u64)j * n + i);
-    } else {
-#pragma unroll
-      for (int e = 0; e < V; e++) wa[e] = wb[e] = 0u;
-    }
-#pragma unroll
-    for (int e = 0; e < V; e++) {
-      a[e][j] = wa[e];
-      b[e][j] = wb[e];
-    }
+    a[j] = j < lim ? __builtin_nontemporal_load(pa + (u64)j * n + i) : 0u;
+    b[j] = j < lim ? __builtin_nontemporal_load(pb + (u64)j * n + i) : 0u;
+  }
+  if (OP == OP_VADD) {
+    mod_add<L>(r, a, b, c.q);
+  } else if (OP == OP_VSUB) {
+    mod_sub<L>(r, a, b, c.q);
+  } else if (OP == OP_VMUL) {
+    barrett_mul<L, KARA>(r, a, b, c.bc);
+  } else {
+    u32 t[L];
+    mont_mul<L>(t, a, c.alpha_m, c.q, c.qinv);  // alpha * x
+    mod_add<L>(r, t, b, c.q);                   // + y
   }
 #pragma unroll
-  for (int e = 0; e < V; e++) {
-    u32 r[L];
-    if (OP == OP_VADD) {
-      mod_add<L>(r, a[e], b[e], c.q);
-    } else if (OP == OP_VSUB) {
-      mod_sub<L>(r, a[e], b[e], c.q);
-    } else if (OP == OP_VMUL) {
-      barrett_mul<L, KARA>(r, a[e], b[e], c.bc);
-    } else {
-      u32 t[L];
-      mont_mul<L>(t, a[e], c.alpha_m, c.q, c.qinv);  // alpha * x
-      mod_add<L>(r, t, b[e], c.q);                   // + y
-    }
-#pragma unroll
-    for (int j = 0; j < L; j++) a[e][j] = r[j];
-  }
-#pragma unroll
-  for (int j = 0; j < L; j++) {
-    if (j < lim) {
-      u32 w[V];
-#pragma unroll
-      for (int e = 0; e < V; e++) w[e] = a[e][j];
-      store_words<V>(pout + (u64)j * n + i, w);
-    }
-  }
-}
-
-// elements per lane.  4 (16-byte accesses) was measured at n = 2^24: vadd at
-// 256 bits took 333 us against 280 us with one element per lane, so every op
-// runs one element per lane; the vector path stays for experiments.
-template <int L, int OP>
-constexpr int blas_vec() {
-  return 1;
-}
-
-template <int L, int OP, bool KARA, int V>
-static int launch_blas_LV(const BlasArgs& a, const BlasC<L>& c, hipStream_t s) {
-  const unsigned T = 256;
-  u64 lanes = (a.n + V - 1) / V;
-  u64 blocks = (lanes + T - 1) / T;
-  hipLaunchKernelGGL((blas_kernel<L, OP, KARA, V>), dim3((unsigned)blocks), dim3(T), 0, s, a.a, a.b, a.out, a.n, c);
-  return (int)hipGetLastError();
+  for (int j = 0; j < L; j++)
+    if (j < lim) __builtin_nontemporal_store(r[j], pout + (u64)j * n + i);
 }
 
 template <int L, int OP, bool KARA>
 static int launch_blas_LK(const BlasArgs& a, const BlasC<L>& c, hipStream_t s) {
-  constexpr int V = blas_vec<L, OP>();
-  if constexpr (V > 1) {
-    const uintptr_t addr = (uintptr_t)a.a | (uintptr_t)a.b | (uintptr_t)a.out;
-    if (a.n % V == 0 && addr % (4 * V) == 0) return launch_blas_LV<L, OP, KARA, V>(a, c, s);
-  }
-  return launch_blas_LV<L, OP, KARA, 1>(a, c, s);
+  const unsigned T = 256;
+  const u64 blocks = (a.n + T - 1) / T;
+  hipLaunchKernelGGL((blas_kernel<L, OP, KARA>), dim3((unsigned)blocks), dim3(T), 0, s, a.a, a.b, a.out, a.n, c);
+  return (int)hipGetLastError();
 }
 
 // mont_mul takes its second operand from VGPRs; alpha is uniform, so keep a

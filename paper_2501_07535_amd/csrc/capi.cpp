@@ -229,12 +229,30 @@ static int check_planes(const NttPlan& p) {
   return 0;
 }
 
+// device copy of host words; on failure *dptr is left NULL and nothing is held
 static int upload(uint32_t** dptr, const std::vector<uint32_t>& host) {
+  *dptr = nullptr;
   int e = (int)hipMalloc((void**)dptr, host.size() * sizeof(uint32_t));
-  if (e) return e;
-  return (int)hipMemcpy(*dptr, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e) {
+    *dptr = nullptr;
+    return e;
+  }
+  e = (int)hipMemcpy(*dptr, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e) {
+    (void)hipFree(*dptr);
+    *dptr = nullptr;
+  }
+  return e;
 }
 
+static void free_tables(DirTables* t) {
+  (void)hipFree(t->tw);
+  (void)hipFree(t->ladder);
+  t->tw = t->ladder = nullptr;
+}
+
+// One direction's ladder and twiddle table.  On failure both are freed (and
+// NULL), so a failed plan build holds no device memory for this direction.
 static int build_tables(NttPlan& p, const HBig& w, DirTables* t) {
   const FieldRaw& f = p.fe->f;
   const HBig& Q = p.fe->Q;
@@ -251,9 +269,16 @@ static int build_tables(NttPlan& p, const HBig& w, DirTables* t) {
   int e = upload(&t->ladder, lad);
   if (e) return hip_fail(e, "ladder upload");
   e = (int)hipMalloc((void**)&t->tw, (size_t)p.n * digit_stride(L) * sizeof(uint32_t));
-  if (e) return set_error(MOMA_E_NOMEM, "twiddle table allocation failed");
+  if (e) {
+    t->tw = nullptr;
+    free_tables(t);
+    return set_error(MOMA_E_NOMEM, "twiddle table allocation failed");
+  }
   e = launch_twiddle_gen(f, p.fe->dc, t->tw, p.n, p.logn, t->ladder, 0);
-  if (e) return hip_fail(e, "twiddle generation launch");
+  if (e) {
+    free_tables(t);
+    return hip_fail(e, "twiddle generation launch");
+  }
   return MOMA_OK;
 }
 
@@ -314,7 +339,10 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   rc = build_tables(*p, W, &p->fwd);
   if (rc) return rc;
   rc = build_tables(*p, Winv, &p->inv);
-  if (rc) return rc;
+  if (rc) {
+    free_tables(&p->fwd);  // (the plan's destructor would too; freed here so the failure path holds nothing)
+    return rc;
+  }
   int e = (int)hipDeviceSynchronize();
   if (e) return hip_fail(e, "plan build");
   std::lock_guard<std::mutex> lk(g_mu);
