@@ -28,23 +28,67 @@ import numpy as np  # noqa: E402
 import moma_inputs as mi  # noqa: E402
 
 # MI355X integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
-# (wave64 full-rate issue; 32-bit integer multiply and multiply-add issue at
-# full rate on gfx950).
+# (full-rate 32-bit lane operations, wave64).  How fast the instructions of a
+# modular multiply actually issue relative to that is measured by the library's
+# own probes (moma_measure_peaks) in every run.
 PEAK_INT_OPS = 256 * 64 * 2.4e9
 PEAK_HBM = 8.0e12
+VALU_SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
 
 
 def word_products(L: int) -> int:
-    """P(L): 32x32-bit word products of one L-limb Montgomery/Barrett multiply."""
+    """P(L): 32x32-bit word products of one L-limb Montgomery multiply
+    (2L^2 + L: the L x L product and the reduction's L x L + L)."""
     return 2 * L * L + L
 
 
-def alg_ops_per_butterfly(L: int) -> int:
-    """Algorithmic integer ops of one butterfly: P(L) products plus A(L) = 2P(L) + 6L
-    add-class ops (two per word product to accumulate it, 3L each for the modular
-    add and subtract)."""
-    P = word_products(L)
-    return P + 2 * P + 6 * L
+def issue_costs(rates: dict) -> tuple[float, float]:
+    """Full-rate issue slots of one word product with its carry step (a
+    v_mad_u64_u32 whose carry-out feeds a v_addc_co_u32) and of one add-class
+    op (an add or subtract with carry), from the measured issue rates."""
+    return 2.0 * rates["add_u32"] / rates["mad_addc_u32"], rates["add_u32"] / rates["add_co_addc_u32"]
+
+
+def butterfly_slots(L: int, rates: dict) -> float:
+    """Issue slots of one butterfly under the op model: one L-limb Montgomery
+    multiply (P(L) word products, each with its carry step) plus a modular add
+    and a modular subtract (3L add-class ops each: the chain, the trial
+    subtraction, the select)."""
+    cm, ca = issue_costs(rates)
+    return word_products(L) * cm + 6 * L * ca
+
+
+def blas_slots(op: str, L: int, rates: dict, karatsuba: bool = False) -> float:
+    """Issue slots per element of one BLAS op under the same op model.  vmul
+    (Barrett): two full L x L products (3 ceil(L/2)^2 word products each by
+    Karatsuba, else L^2) and the low half of r2 * q (L(L+1)/2), plus 3L for the
+    subtraction and correction; axpy: a Montgomery multiply by alpha (P(L))
+    with its correction (2L) and a modular add (3L); vadd/vsub: 3L."""
+    cm, ca = issue_costs(rates)
+    if op in ("vadd", "vsub"):
+        return 3 * L * ca
+    if op == "vmul":
+        h, g = (L + 1) // 2, L // 2
+        full = 2 * h * h + g * g if karatsuba else L * L
+        return (2 * full + L * (L + 1) // 2) * cm + 3 * L * ca
+    return word_products(L) * cm + 5 * L * ca
+
+
+def host_cpu() -> dict:
+    """CPU model and core counts of the host the oracle baseline ran on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
 
 
 def parse():
@@ -72,6 +116,9 @@ def parse():
                     help="instead of the headline line, print one JSON line per modular BLAS op and width "
                          "(vadd/vsub/vmul/axpy at n=2^24, 256/384/768 bits)")
     ap.add_argument("--blas-logn", type=int, default=24)
+    ap.add_argument("--peaks", action="store_true",
+                    help="instead of the headline line, print the measured issue rates and HBM bandwidths that "
+                         "price the roofline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -86,6 +133,7 @@ def sweep(args):
     import paper_2501_07535_amd as moma
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    rates = moma.measure_peaks()
     for lam, logn in [(256, l) for l in range(16, 25)] + [(128, 20), (384, 20), (1024, 20)]:
         f = mi.find_prime(lam, 0)
         L, n, q = f.limbs, 1 << logn, f.q
@@ -110,19 +158,10 @@ def sweep(args):
         print(json.dumps({"lambda": lam, "limbs": L, "log2_n": logn, "fwd_us": round(us, 2),
                           "gbutterfly_s": round(B / us / 1e3, 3), "steady_state": st,
                           "schedule": list(moma.ntt_get_schedule(q, w, n, L)),
-                          "int_ops_frac": round(alg_ops_per_butterfly(L) * B / (us * 1e-6) / PEAK_INT_OPS, 4),
+                          "alu_frac": round(butterfly_slots(L, rates) * B / (us * 1e-6) / PEAK_INT_OPS, 4),
                           "sampled_vs_oracle": ok}), flush=True)
         del dx, dy
         moma.shutdown()
-
-
-def blas_ops(op: str, L: int) -> int:
-    """Algorithmic integer ops per element: a modular add or subtract is 3L
-    add-class ops (add, trial subtract, select); a modular multiply is
-    3 P(L) + 3L (P(L) word products, two accumulate ops per product, one
-    correction); axpy adds a modular add."""
-    P = word_products(L)
-    return {"vadd": 3 * L, "vsub": 3 * L, "vmul": 3 * P + 3 * L, "axpy": 3 * P + 6 * L}[op]
 
 
 def blas(args):
@@ -136,6 +175,7 @@ def blas(args):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     n = 1 << args.blas_logn
+    rates = moma.measure_peaks()
     idx = np.array([0, 1, n // 3, n // 2 + 7, n - 2, n - 1], dtype=np.int64)
     for lam in (256, 384, 768):
         f = mi.find_prime(lam, 0)
@@ -174,11 +214,11 @@ def blas(args):
             want = {"vadd": lambda: oracle.vadd(q, L, a, bb), "vsub": lambda: oracle.vsub(q, L, a, bb),
                     "vmul": lambda: oracle.vmul(q, L, a, bb), "axpy": lambda: oracle.axpy(q, L, alpha, a, bb)}[op]()
             byt = 3 * n * 4 * L
-            ops = blas_ops(op, L) * n
-            t_hbm, t_alu = byt / PEAK_HBM, ops / PEAK_INT_OPS
+            slots = blas_slots(op, L, rates, karatsuba=(op == "vmul" and tuned["chosen"] == moma.VMUL_KARATSUBA)) * n
+            t_hbm, t_alu = byt / PEAK_HBM, slots / PEAK_INT_OPS
             bound = "hbm" if t_hbm >= t_alu else "alu"
             print(json.dumps({"op": op, "lambda": lam, "limbs": L, "log2_n": args.blas_logn, "us": round(us, 2),
-                              "GB_s": round(byt / us / 1e3, 1), "Tops_s": round(ops / us / 1e6, 3),
+                              "GB_s": round(byt / us / 1e3, 1), "Tslots_s": round(slots / us / 1e6, 3),
                               "bound": bound, "roofline_us": round(max(t_hbm, t_alu) * 1e6, 2),
                               "frac": round(max(t_hbm, t_alu) * 1e6 / us, 4),
                               "hbm_frac": round(t_hbm * 1e6 / us, 4), "alu_frac": round(t_alu * 1e6 / us, 4),
@@ -186,6 +226,24 @@ def blas(args):
                               "sampled_vs_oracle": bool((got == want).all())}), flush=True)
         del da, db, dc
         torch.cuda.empty_cache()
+
+
+def peaks():
+    """The library's issue-rate and bandwidth probes, as rates and as fractions
+    of the vendor peaks (39.32 T full-rate lane operations/s, 8 TB/s)."""
+    import paper_2501_07535_amd as moma
+    r = moma.measure_peaks()
+    cm, ca = issue_costs(r)
+    out = {"rates_Tops": {k: round(r[k] / 1e12, 3) for k in ("add_u32", "add_co_addc_u32", "mad_u64_u32",
+                                                              "mad_addc_u32", "mul_lo_u32", "mul_hi_u32")},
+           "of_full_rate": {k: round(r[k] / PEAK_INT_OPS, 4) for k in ("add_u32", "add_co_addc_u32", "mad_u64_u32",
+                                                                     "mad_addc_u32", "mul_lo_u32", "mul_hi_u32")},
+           "hbm_TBs": {"copy": round(r["hbm_copy"] / 1e12, 3), "triad": round(r["hbm_triad"] / 1e12, 3)},
+           "of_hbm_peak": {"copy": round(r["hbm_copy"] / PEAK_HBM, 4), "triad": round(r["hbm_triad"] / PEAK_HBM, 4)},
+           "slots_per_word_product_with_carry": round(cm, 4), "slots_per_add_op": round(ca, 4),
+           "slots_per_butterfly": {str(L): round(butterfly_slots(L, r), 1) for L in (2, 4, 8, 12, 16, 24, 32)},
+           "compute_units": r["compute_units"]}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -199,6 +257,9 @@ def main():
         return
     if args.blas:
         blas(args)
+        return
+    if args.peaks:
+        peaks()
         return
     import torch
 
@@ -269,10 +330,20 @@ def main():
 
     B = n // 2 * logn
     gbfly = B / (ms_step * 1e-3) / 1e9
-    ops = alg_ops_per_butterfly(L) * B
+    # the pass kernel's average duration: HIP events over the timed region on
+    # the stream the library launches on, divided by the launches it holds
     launch_ms = ms_step / launches
-    achieved = ops / launches / (launch_ms * 1e-3) / 1e12
+    # issue rates measured on this device after the timed region
+    rates = moma.measure_peaks()
+    slots = butterfly_slots(L, rates)
+    achieved = slots * B / launches / (launch_ms * 1e-3) / 1e12
     peak = PEAK_INT_OPS / 1e12
+    counters = committed_counters(lam, logn, moma.ntt_get_schedule(q, w, n, L), plan["stages"])
+    valu_issue = None
+    if counters and counters.get("sq_insts_valu_per_launch"):
+        # wave instructions x 4 cycles each over the SIMD-cycles of one launch
+        valu_issue = counters["sq_insts_valu_per_launch"] * 4 / (VALU_SIMDS * CLOCK_HZ * launch_ms * 1e-3)
+    cm, ca = issue_costs(rates)
 
     if args.calib_copy_mib:
         src = torch.zeros(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
@@ -315,10 +386,21 @@ def main():
                    "layout": "limb-planar", "twiddles": "precomputed table"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "Tops/s",
                      "frac": round(achieved / peak, 4),
-                     "traffic": measured_traffic(lam, logn, moma.ntt_get_schedule(q, w, n, L), plan["stages"]),
-                     "kernel": f"ntt_pass_kernel<{L}>", "launches_per_step": launches,
+                     "traffic": counters["traffic_bytes_per_launch"] if counters else None,
+                     "kernel": f"ntt_pass_kernel<{L}, radix_log {moma.ntt_get_schedule(q, w, n, L)[3]}>",
+                     "launches_per_step": launches,
                      "avg_launch_us": round(launch_ms * 1e3, 3),
-                     "ops_per_butterfly": alg_ops_per_butterfly(L), "pass_stages": plan["stages"],
+                     "avg_launch_us_from": "HIP events over the timed region / launches",
+                     "op_model": {"word_products_per_butterfly": word_products(L),
+                                  "add_class_ops_per_butterfly": 6 * L,
+                                  "slots_per_word_product": round(cm, 4), "slots_per_add_op": round(ca, 4),
+                                  "slots_per_butterfly": round(slots, 2)},
+                     "measured_rates_Tops": {k: round(rates[k] / 1e12, 3) for k in
+                                             ("add_u32", "add_co_addc_u32", "mad_u64_u32", "mad_addc_u32",
+                                              "mul_lo_u32", "mul_hi_u32")},
+                     "hbm_copy_TBs": round(rates["hbm_copy"] / 1e12, 3),
+                     "valu_issue_frac": round(valu_issue, 4) if valu_issue else None,
+                     "pass_stages": plan["stages"],
                      "schedule": list(moma.ntt_get_schedule(q, w, n, L))},
         "cpu_baseline": cpu,
         "extras": {"fwd_us": round(ms_step * 1e3, 3), "inv_us": round(ms_inv * 1e3, 3) if ms_inv else None,
@@ -337,13 +419,14 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def measured_traffic(lam, logn, schedule, stages):
-    """HBM bytes per pass-kernel launch from the committed rocprofv3 counters, if
-    they were taken on the current kernel sources with the same launches (pass
-    stages, columns per tile, threads and register radix; the tile size bound
-    itself does not change the launches)."""
+def committed_counters(lam, logn, schedule, stages):
+    """The pass kernel's rocprofv3 counters committed under profiles/ (HBM bytes
+    per launch from FETCH_SIZE and WRITE_SIZE, VALU wave instructions per
+    launch), if they were taken on the current kernel sources with the same
+    launches (pass stages, columns per tile, threads and register radix; the
+    tile size bound itself does not change the launches); else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"ntt_traffic_L{(lam + 31) // 32}_{lam}bit_n2e{logn}.json")
+    path = os.path.join(ROOT, "profiles", f"ntt_counters_L{(lam + 31) // 32}_{lam}bit_n2e{logn}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -353,7 +436,7 @@ def measured_traffic(lam, logn, schedule, stages):
     same = (list(rec["pass_stages"]) == list(stages) and list(rec["schedule"])[1:] == list(schedule)[1:])
     if h.hexdigest() != rec["kernel_sources_sha256"] or not same:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec
 
 
 def small_call_latency(moma, torch, stream, reps=100, warmup=10):
@@ -552,7 +635,7 @@ def cpu_baseline(q, L, w, x, n, logn, seconds):
             break
     per = el / reps
     return {"value": round(n // 2 * logn / per / 1e9, 6), "unit": "Gbutterfly/s", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", **host_cpu(),
             "sample": f"the full n=2^{logn} forward transform (oracle radix-2, division-based modmul), "
                       f"{reps} repetitions, {el:.1f} s"}
 

@@ -156,6 +156,15 @@ _lib.moma_last_error_detail.restype = ctypes.c_char_p
 _lib.moma_version.restype = ctypes.c_char_p
 _lib.moma_shutdown.restype = None
 
+class _PeakRates(ctypes.Structure):
+    _fields_ = [("add_u32", ctypes.c_double), ("add_co_addc_u32", ctypes.c_double), ("mad_u64_u32", ctypes.c_double),
+                ("mad_addc_u32", ctypes.c_double), ("mul_lo_u32", ctypes.c_double), ("mul_hi_u32", ctypes.c_double),
+                ("hbm_copy", ctypes.c_double), ("hbm_triad", ctypes.c_double), ("compute_units", ctypes.c_uint32)]
+
+
+_lib.moma_measure_peaks.argtypes = [ctypes.POINTER(_PeakRates), ctypes.c_uint64, _vp]
+_lib.moma_measure_peaks.restype = ctypes.c_int
+
 MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
@@ -166,7 +175,7 @@ EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vad
             "moma_costmodel_features", "moma_costmodel_train", "moma_costmodel_predict", "moma_costmodel_save",
             "moma_costmodel_load", "moma_costmodel_clear", "moma_mlp_nparams", "moma_mlp_forward", "moma_mlp_grad",
             "moma_mlp_adam", "moma_check_canonical", "moma_set_input_check", "moma_pack_planar",
-            "moma_unpack_planar", "moma_shutdown")
+            "moma_unpack_planar", "moma_measure_peaks", "moma_shutdown")
 
 
 class MomaError(RuntimeError):
@@ -565,6 +574,14 @@ def mlp_grad(params, x, t, grad, loss, stream=None):
 def mlp_adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(_lib.moma_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, beta1,
                               beta2, eps, _stream(stream)))
+
+
+def measure_peaks(hbm_bytes: int = 0, stream=None) -> dict:
+    """Measured issue rates (lane operations per second) and HBM bandwidths
+    (bytes per second); synchronises the stream."""
+    r = _PeakRates()
+    _check(_lib.moma_measure_peaks(ctypes.byref(r), hbm_bytes, _stream(stream)))
+    return {name: getattr(r, name) for name, _ in _PeakRates._fields_}
 
 
 def shutdown():
