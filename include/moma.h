@@ -185,6 +185,29 @@ int moma_ntt_cyclic_mul(const uint32_t* q, const uint32_t* omega, uint64_t n, ui
                         const uint32_t* d_b, uint32_t* d_out, void* stream);
 
 /*
+ * The cyclic product above for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result (bit for bit) and preconditions as
+ * moma_ntt_cyclic_mul, and the same kernels; it calls no hipMalloc, hipFree or
+ * other allocating routine.  Differences:
+ *   - the plan for (q, omega, n, limbs) on the current device must already
+ *     exist (moma_ntt_prepare, or any earlier call that built it); otherwise
+ *     MOMA_E_ARG and nothing is enqueued;
+ *   - the two spectra, 2 * n * L words (L = compute limbs; a full-width
+ *     modulus also stages n * L words), live in a fixed library-wide device
+ *     array of MOMA_NOALLOC_SCRATCH_WORDS 32-bit words (64 MiB) that each GPU
+ *     holds until the process ends; a request needing more is MOMA_E_ARG
+ *     (at 256 bits, L = 8, n may be up to 2^20).
+ * Every call on one GPU shares that array and leaves its contents behind:
+ * calls that overlap on one GPU (other streams, other host threads) race and
+ * give undefined results.  With the input check on, the per-workgroup counts
+ * also use the array, and the call waits for its stream before enqueueing.
+ */
+#define MOMA_NOALLOC_SCRATCH_WORDS (1u << 24)
+int moma_ntt_cyclic_mul_noalloc(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs,
+                                const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, void* stream);
+
+/*
  * Build (or look up) the plan for (q, omega, n, limbs) without running a
  * transform, so timed loops exclude plan creation.  Returns MOMA_OK or an
  * error code for invalid parameters.

@@ -58,8 +58,9 @@ _lib.moma_vmul_set_variant.argtypes = [_u32p, ctypes.c_uint32, ctypes.c_uint32]
 _lib.moma_vmul_get_variant.argtypes = [_u32p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
 _lib.moma_vmul_tune.argtypes = [_u32p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float),
                                 ctypes.POINTER(ctypes.c_uint32)]
-_lib.moma_ntt_cyclic_mul.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp, _vp]
-_lib.moma_ntt_cyclic_mul.restype = ctypes.c_int
+for _name in ("moma_ntt_cyclic_mul", "moma_ntt_cyclic_mul_noalloc"):
+    getattr(_lib, _name).argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp, _vp]
+    getattr(_lib, _name).restype = ctypes.c_int
 _lib.moma_ntt_prepare.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32]
 _lib.moma_ntt_prepare.restype = ctypes.c_int
 _lib.moma_ntt_describe.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, _u32p, _u32p, ctypes.c_uint32,
@@ -168,7 +169,7 @@ _lib.moma_measure_peaks.restype = ctypes.c_int
 MOMA_OK, MOMA_E_ARG, MOMA_E_MODULUS, MOMA_E_ROOT, MOMA_E_NOMEM, MOMA_E_HIP, MOMA_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = ("moma_strerror", "moma_last_error_detail", "moma_version", "moma_vadd", "moma_vsub", "moma_vmul",
-            "moma_axpy", "moma_vmul_set_variant", "moma_vmul_get_variant", "moma_vmul_tune", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_cyclic_mul", "moma_ntt_prepare", "moma_ntt_describe",
+            "moma_axpy", "moma_vmul_set_variant", "moma_vmul_get_variant", "moma_vmul_tune", "moma_ntt_fwd", "moma_ntt_inv", "moma_ntt_cyclic_mul", "moma_ntt_cyclic_mul_noalloc", "moma_ntt_prepare", "moma_ntt_describe",
             "moma_ntt_set_schedule", "moma_ntt_get_schedule", "moma_ntt_default_schedule", "moma_batch_create", "moma_batch_run",
             "moma_batch_info", "moma_batch_destroy", "moma_ntt_tune", "moma_ntt_candidates", "moma_tune_db_count",
             "moma_tune_db_get", "moma_tune_db_clear", "moma_tune_db_save", "moma_tune_db_load",
@@ -369,6 +370,22 @@ def ntt_cyclic_mul(a, b, q: int, omega: int, out=None, stream=None):
     _check(_lib.moma_ntt_cyclic_mul(_words(q, limbs), _words(omega, limbs), n, limbs, a.data_ptr(), b.data_ptr(),
                                     out.data_ptr(), _stream(stream)))
     return out
+
+
+def ntt_cyclic_mul_noalloc(a, b, q: int, omega: int, out, stream=None):
+    """The cyclic product through the entry point that allocates no device
+    memory: the plan must exist (ntt_prepare) and `out` is required; the
+    spectra live in the library's fixed scratch array (NOALLOC_SCRATCH_WORDS)."""
+    _dev(a, "a"); _dev(b, "b"); _dev(out, "out")
+    if a.shape != b.shape or out.shape != a.shape:
+        raise ValueError("a, b and out must have the same shape")
+    limbs, n = a.shape
+    _check(_lib.moma_ntt_cyclic_mul_noalloc(_words(q, limbs), _words(omega, limbs), n, limbs, a.data_ptr(),
+                                            b.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_WORDS = 1 << 24  # MOMA_NOALLOC_SCRATCH_WORDS
 
 
 def ntt_prepare(q: int, omega: int, n: int, limbs: int):

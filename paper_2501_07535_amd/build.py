@@ -27,7 +27,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["ntt_inst_e.hip", "ntt_inst_d.hip", "ntt_inst_c.hip", "ntt_inst_b.hip", "ntt_inst_a.hip", "ntt.hip", "blas.hip", "mlp.hip", "probe.hip",
+SOURCES = ["ntt_inst_e.hip", "ntt_inst_d.hip", "ntt_inst_c.hip", "ntt_inst_b.hip", "ntt_inst_a.hip", "ntt.hip", "blas.hip", "mlp.hip", "probe.hip", "noalloc.hip",
            "capi.cpp", "batch.cpp", "tune.cpp", "costmodel.cpp"]
 
 

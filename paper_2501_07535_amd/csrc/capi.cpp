@@ -282,6 +282,33 @@ static int build_tables(NttPlan& p, const HBig& w, DirTables* t) {
   return MOMA_OK;
 }
 
+static std::vector<uint32_t> plan_key(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, int dev) {
+  std::vector<uint32_t> key(q, q + limbs);
+  key.insert(key.end(), omega, omega + limbs);
+  key.push_back(limbs);
+  key.push_back((uint32_t)n);
+  key.push_back((uint32_t)(n >> 32));
+  key.push_back((uint32_t)dev);
+  return key;
+}
+
+int find_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, std::shared_ptr<NttPlan>* out) {
+  if (!q || !omega) return set_error(MOMA_E_ARG, "q or omega is NULL");
+  if (limbs < MOMA_MIN_LIMBS || limbs > MOMA_MAX_LIMBS)
+    return set_error(MOMA_E_ARG, "limbs must be in [2, 32], got " + std::to_string(limbs));
+  if (n < 2 || (n & (n - 1)) || n > (1ull << MOMA_MAX_LOG_N))
+    return set_error(MOMA_E_ARG, "n must be a power of two in [2, 2^26], got " + std::to_string(n));
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::vector<uint32_t> key = plan_key(q, omega, n, limbs, dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_plans.find(key);
+  if (it == g_plans.end())
+    return set_error(MOMA_E_ARG, "no plan for these arguments on this device: build it first (moma_ntt_prepare)");
+  *out = it->second;
+  return MOMA_OK;
+}
+
 int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, std::shared_ptr<NttPlan>* out) {
   if (!omega) return set_error(MOMA_E_ARG, "omega is NULL");
   if (n < 2 || (n & (n - 1)) || n > (1ull << MOMA_MAX_LOG_N))
@@ -291,12 +318,7 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   if (rc) return rc;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  std::vector<uint32_t> key(q, q + limbs);
-  key.insert(key.end(), omega, omega + limbs);
-  key.push_back(limbs);
-  key.push_back((uint32_t)n);
-  key.push_back((uint32_t)(n >> 32));
-  key.push_back((uint32_t)dev);
+  std::vector<uint32_t> key = plan_key(q, omega, n, limbs, dev);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.find(key);
@@ -462,7 +484,13 @@ int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hi
 // plan's spectra buffer, and the inverse transform's first pass multiplies
 // them pointwise while loading (digit-form Montgomery, a factor 2^(-bD)); its
 // last pass scales by n^-1 2^(bD), which cancels that factor.
-int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s) {
+uint64_t cyclic_mul_scratch_words(const NttPlan& p) {
+  const FieldRaw& f = p.fe->f;
+  return (uint64_t)(f.Ls < f.L ? 3 : 2) * p.n * (uint64_t)f.L;
+}
+
+int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s,
+                   uint32_t* ext) {
   const FieldRaw& f = p.fe->f;
   const bool full = f.Ls < f.L;
   std::vector<NttPass> passes;
@@ -472,11 +500,17 @@ int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_
     std::lock_guard<std::mutex> lk(p.mu);
     passes = p.passes;
     sched = p.sched;
-    int rc = plan_buffer(p, &p.spectra, 2, "spectra");
-    if (!rc && full) rc = plan_buffer(p, &p.stage, 1, "staging");
-    if (rc) return rc;
-    spec = p.spectra;
-    stage = p.stage;
+    if (ext) {
+      // caller-provided scratch: [spectrum a | spectrum b | stage (full width)]
+      spec = ext;
+      stage = ext + 2 * (size_t)p.n * f.L;
+    } else {
+      int rc = plan_buffer(p, &p.spectra, 2, "spectra");
+      if (!rc && full) rc = plan_buffer(p, &p.stage, 1, "staging");
+      if (rc) return rc;
+      spec = p.spectra;
+      stage = p.stage;
+    }
   }
   uint32_t* sa = spec;
   uint32_t* sb = spec + (size_t)p.n * f.L;
@@ -518,26 +552,29 @@ bool input_check_on() {
   return g_check_inputs == 1;
 }
 
-int count_noncanonical(const FieldRaw& f, const uint32_t* d_x, uint64_t n, hipStream_t s, uint64_t* bad) {
+int count_noncanonical(const FieldRaw& f, const uint32_t* d_x, uint64_t n, hipStream_t s, uint64_t* bad,
+                       uint32_t* d_part) {
   *bad = 0;
   if (n == 0) return MOMA_OK;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (n + 255) / 256);
-  uint32_t* d_part = nullptr;
-  if (hipMalloc((void**)&d_part, blocks * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, "input check buffer");
+  const bool own = d_part == nullptr;
+  if (own && hipMalloc((void**)&d_part, blocks * sizeof(uint32_t)))
+    return set_error(MOMA_E_NOMEM, "input check buffer");
   std::vector<uint32_t> part(blocks, 0);
   int e = launch_count_noncanonical(f.q, f.Ls, d_x, n, d_part, blocks, s);
   if (!e) e = (int)hipMemcpyAsync(part.data(), d_part, blocks * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (!e) e = (int)hipStreamSynchronize(s);
-  (void)hipFree(d_part);
+  if (own) (void)hipFree(d_part);
   if (e) return hip_fail(e, "input check");
   for (uint32_t v : part) *bad += v;
   return MOMA_OK;
 }
 
-int check_inputs(const FieldRaw& f, const uint32_t* const* d_x, int nx, uint64_t n, hipStream_t s) {
+int check_inputs(const FieldRaw& f, const uint32_t* const* d_x, int nx, uint64_t n, hipStream_t s,
+                 uint32_t* d_part) {
   for (int i = 0; i < nx; i++) {
     uint64_t bad = 0;
-    int rc = count_noncanonical(f, d_x[i], n, s, &bad);
+    int rc = count_noncanonical(f, d_x[i], n, s, &bad, d_part);
     if (rc) return rc;
     if (bad)
       return set_error(MOMA_E_ARG, "input " + std::to_string(i) + " holds " + std::to_string(bad) +

@@ -64,7 +64,15 @@ int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>
 NttSchedule default_schedule(int L, uint32_t logn);
 NttSchedule batch_schedule(int L, uint32_t logn);
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s);
-int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s);
+// ext: NULL, or caller-provided device scratch of cyclic_mul_scratch_words(p)
+// words used in place of the plan's spectra (and staging) buffers, so the call
+// allocates nothing
+int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s,
+                   uint32_t* ext = nullptr);
+uint64_t cyclic_mul_scratch_words(const NttPlan& p);
+// the cached plan for these arguments, or MOMA_E_ARG when none has been built
+// (allocates no device memory)
+int find_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, std::shared_ptr<NttPlan>* out);
 // batched BLAS (blas.hip): one record per job, its constants, and items
 // (record, block of 256 elements)
 struct BlasJobRec {
@@ -91,8 +99,11 @@ int launch_count_noncanonical(const uint32_t* q, int ls, const uint32_t* d_x, ui
 int launch_layout(const uint32_t* src, uint32_t* dst, uint64_t n, uint32_t L, bool to_planar, hipStream_t s);
 // the input check of every entry point (MOMA_CHECK_INPUTS / moma_set_input_check)
 bool input_check_on();
-int count_noncanonical(const FieldRaw& f, const uint32_t* d_x, uint64_t n, hipStream_t s, uint64_t* bad);
-int check_inputs(const FieldRaw& f, const uint32_t* const* d_x, int nx, uint64_t n, hipStream_t s);
+// d_part: NULL (a buffer is allocated for the call) or at least 1024 device words
+int count_noncanonical(const FieldRaw& f, const uint32_t* d_x, uint64_t n, hipStream_t s, uint64_t* bad,
+                       uint32_t* d_part = nullptr);
+int check_inputs(const FieldRaw& f, const uint32_t* const* d_x, int nx, uint64_t n, hipStream_t s,
+                 uint32_t* d_part = nullptr);
 // tuner (tune.cpp)
 std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn);
 bool tune_db_best(const std::string& dev, int L, uint32_t logn, NttSchedule* out);
