@@ -108,7 +108,8 @@ def parse():
                     help="tile_log,col_log,threads,radix_log: use this launch shape instead of autotuning")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line, print one JSON line per size of the transform sweep "
-                         "(2^16..2^24 at 256 bits, 2^20 at 128/384/1024 bits)")
+                         "(2^16..2^24 at 256 bits, 2^20 at 128/384/1024 bits, and 2^20 with full-width "
+                         "256- and 1024-bit moduli)")
     ap.add_argument("--forward-only", action="store_true",
                     help="time only the headline forward transform (no default-schedule, inverse or cyclic-product "
                          "timing): every transform kernel launched is a headline pass, for counter collection")
@@ -134,8 +135,12 @@ def sweep(args):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     rates = moma.measure_peaks()
-    for lam, logn in [(256, l) for l in range(16, 25)] + [(128, 20), (384, 20), (1024, 20)]:
-        f = mi.find_prime(lam, 0)
+    # (class, log2 n, modulus bits): the paper's lam - 4 bit moduli, then full-width
+    # moduli (bitlen q = lam, no headroom) at 256 and 1024 bits
+    shapes = [(256, l, None) for l in range(16, 25)] + [(128, 20, None), (384, 20, None), (1024, 20, None),
+                                                         (256, 20, 256), (1024, 20, 1024)]
+    for lam, logn, bits in shapes:
+        f = mi.find_prime(lam, 0, bits=bits) if bits else mi.find_prime(lam, 0)
         L, n, q = f.limbs, 1 << logn, f.q
         w = f.root(n)
         x = mi.residues(f, n, L, 2, logn)
@@ -155,7 +160,8 @@ def sweep(args):
         st = steady_state(moma, torch, stream, dx, q, w, n, L, logn,
                           ks=tuple(sorted({k for k in (1, 4, 16, 64) if k <= kmax} | {kmax})))
         B = n // 2 * logn
-        print(json.dumps({"lambda": lam, "limbs": L, "log2_n": logn, "fwd_us": round(us, 2),
+        print(json.dumps({"lambda": lam, "limbs": L, "q_bits": q.bit_length(), "full_width": bool(bits),
+                          "log2_n": logn, "fwd_us": round(us, 2),
                           "gbutterfly_s": round(B / us / 1e3, 3), "steady_state": st,
                           "schedule": list(moma.ntt_get_schedule(q, w, n, L)),
                           "alu_frac": round(butterfly_slots(L, rates) * B / (us * 1e-6) / PEAK_INT_OPS, 4),

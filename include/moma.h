@@ -24,11 +24,13 @@
  * Preconditions checked on the host before anything is enqueued
  *   2 <= limbs <= 32; q odd, q >= 3, bitlen(q) <= 32*limbs.  The paper's
  *   moduli are four bits short of the class width (Section 5.2), which
- *   leaves headroom for lazy reduction; a modulus within 4 bits of the
- *   storage width ("full width") computes in one more internal limb, and the
- *   transforms stage such vectors through library-owned buffers of that
- *   width (one extra copy in and out).  A full-width 1024-bit modulus would
- *   need 33 internal limbs and is MOMA_E_UNSUPPORTED;
+ *   leaves headroom for lazy reduction and Barrett's pre-scaled modulus; a
+ *   modulus within 4 bits of the storage width ("full width", up to 1024
+ *   bits in 32 limbs) computes in the same limbs with canonical operands and
+ *   Montgomery products that carry out of the top limb (Section 5.2 names
+ *   Montgomery multiplication for such moduli): vmul then takes two
+ *   Montgomery products (the product variant does not apply), and the
+ *   transforms use radix-2 and radix-4 units only;
  *   n a power of two, 2 <= n <= 2^26 (BLAS: any n >= 0);
  *   omega of multiplicative order exactly n (omega^{n/2} == q - 1), which
  *   also implies n | q - 1 for prime q.  Primality of q is the caller's
@@ -193,11 +195,10 @@ int moma_ntt_cyclic_mul(const uint32_t* q, const uint32_t* omega, uint64_t n, ui
  *   - the plan for (q, omega, n, limbs) on the current device must already
  *     exist (moma_ntt_prepare, or any earlier call that built it); otherwise
  *     MOMA_E_ARG and nothing is enqueued;
- *   - the two spectra, 2 * n * L words (L = compute limbs; a full-width
- *     modulus also stages n * L words), live in a fixed library-wide device
- *     array of MOMA_NOALLOC_SCRATCH_WORDS 32-bit words (64 MiB) that each GPU
- *     holds until the process ends; a request needing more is MOMA_E_ARG
- *     (at 256 bits, L = 8, n may be up to 2^20).
+ *   - the two spectra, 2 * n * L words (L = compute limbs), live in a fixed
+ *     library-wide device array of MOMA_NOALLOC_SCRATCH_WORDS 32-bit words
+ *     (64 MiB) that each GPU holds until the process ends; a request needing
+ *     more is MOMA_E_ARG (at 256 bits, L = 8, n may be up to 2^20).
  * Every call on one GPU shares that array and leaves its contents behind:
  * calls that overlap on one GPU (other streams, other host threads) race and
  * give undefined results.  With the input check on, the per-workgroup counts

@@ -31,7 +31,7 @@ namespace moma {
 
 struct BatchLaunch {
   int L;
-  bool mul, variant;
+  bool mul, variant, fw;
   uint32_t radix_log, threads, grid, nitems;
   size_t lds;
   const NttPassArgs* d_passes;
@@ -45,16 +45,9 @@ struct ZeroFill {
   int from, to;
 };
 
-// full-width moduli: a job's Ls storage planes copied into (and back out of)
-// an L-plane stage whose top plane is zero
-struct PlaneCopy {
-  uint32_t* dst;
-  const uint32_t* src;
-  uint64_t words;
-};
-
 struct BlasLaunch {
   int op, L;
+  bool fw;
   uint32_t variant, nitems;
   const void* d_recs;
   const void* d_consts;
@@ -67,8 +60,6 @@ struct BatchImpl {
   std::vector<BatchLaunch> launches;
   std::vector<BlasLaunch> blas;
   std::vector<ZeroFill> fills;
-  std::vector<PlaneCopy> copy_in, copy_out;
-  std::vector<ZeroFill> stage_tops;
   // every job's inputs, counted before a run when the input check is on
   struct Input {
     std::shared_ptr<FieldEntry> fe;
@@ -112,8 +103,9 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
   // product: a kernel variant of its own), and the tile's LDS bytes (a launch
   // reserves its largest tile for every workgroup, so mixing sizes would cut
   // the occupancy of the smaller tiles), and whether the pass runs the kernel
-  // variant with the direct first round and the cross-lane last stage
-  typedef std::tuple<int, uint32_t, uint32_t, bool, size_t, bool> GKey;
+  // variant with the direct first round and the cross-lane last stage, and
+  // whether the modulus is full width (kernels of their own)
+  typedef std::tuple<int, uint32_t, uint32_t, bool, size_t, bool, bool> GKey;
   std::map<GKey, Group> groups;
   NttConsts none;
   memset(&none, 0, sizeof(none));
@@ -122,7 +114,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
                  const NttConsts& nc, bool scale, const uint32_t* in, const uint32_t* in2, uint32_t* first_out,
                  uint32_t* out, uint32_t phase0) {
     const FieldRaw& f = p.fe->f;
-    size_t cb = ntt_consts_bytes(f.L);
+    size_t cb = ntt_consts_bytes(f.L, f.fw != 0);
     for (size_t i = 0; i < passes.size(); i++) {
       const NttPass& ps = passes[i];
       const size_t tile_bytes = ((size_t)1 << (ps.k + ps.logc)) * f.L * sizeof(uint32_t);
@@ -138,8 +130,9 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       a.logc = ps.logc;
       a.last = (i + 1 == passes.size()) ? 1u : 0u;
       a.scale = (scale && i + 1 == passes.size()) ? 1u : 0u;
-      const bool variant = ntt_batch_variant(f.L, sched.radix_log, sched.threads, &a);
-      Group& g = groups[GKey(f.L, sched.radix_log, sched.threads, i == 0 && in2 != nullptr, tile_bytes, variant)];
+      const bool variant = !f.fw && ntt_batch_variant(f.L, sched.radix_log, sched.threads, &a);
+      Group& g = groups[GKey(f.L, sched.radix_log, sched.threads, i == 0 && in2 != nullptr, tile_bytes, variant,
+                             f.fw != 0)];
       uint32_t rec = (uint32_t)g.recs.size();
       g.recs.push_back(a);
       size_t off = g.consts.size();
@@ -154,14 +147,14 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       g.lds[ph] = std::max(g.lds[ph], bytes);
     }
   };
-  // BLAS jobs: per (op, compute limbs, vmul variant) the job records, their
-  // constants and the (record, 256-element block) items
+  // BLAS jobs: per (op, compute limbs, vmul variant, full width) the job
+  // records, their constants and the (record, 256-element block) items
   struct BGroup {
     std::vector<BlasJobRec> recs;
     std::vector<uint8_t> consts;
     std::vector<uint2> items;
   };
-  std::map<std::tuple<int, int, uint32_t>, BGroup> bgroups;
+  std::map<std::tuple<int, int, uint32_t, bool>, BGroup> bgroups;
   for (uint32_t j = 0; j < njobs; j++) {
     const moma_ntt_job_t& job = jobs[j];
     const std::string tag = "job " + std::to_string(j) + ": ";
@@ -181,12 +174,12 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       a.out = job.d_out;
       a.n = job.n;
       a.ls = (uint32_t)fe->f.Ls;
-      if (op == OP_VMUL) a.variant = vmul_variant(fe->f.L);
+      if (op == OP_VMUL && !fe->f.fw) a.variant = vmul_variant(fe->f.L);
       if (op == OP_AXPY) {
         rc = axpy_alpha(*fe, job.alpha, job.limbs, a.alpha_m);
         if (rc) return set_error(rc, tag + g_detail);
       }
-      BGroup& g = bgroups[std::make_tuple(op, fe->f.L, a.variant)];
+      BGroup& g = bgroups[std::make_tuple(op, fe->f.L, a.variant, fe->f.fw != 0)];
       const uint32_t rec = (uint32_t)g.recs.size();
       g.recs.push_back({job.d_in, job.d_in2, job.d_out, job.n});
       size_t cb = blas_consts_bytes(fe->f.L), off = g.consts.size();
@@ -226,14 +219,13 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       NttSchedule ds = batch_schedule(f.L, p->logn);
       std::vector<NttPass> dp;
       std::string keep = g_detail;
-      if (plan_passes(f.L, p->logn, ds, &dp) == MOMA_OK) {
+      if (plan_passes(f.L, p->logn, ds, &dp, f.fw) == MOMA_OK) {
         sched = ds;
         passes = dp;
       }
       g_detail = keep;
     }
     const size_t plane_words = (size_t)p->n * f.L;
-    const bool full = f.Ls < f.L;
     auto alloc = [&](size_t words, uint32_t** outp) -> int {
       void* s = nullptr;
       if (hipMalloc(&s, words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, tag + "job buffers");
@@ -241,50 +233,25 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       *outp = (uint32_t*)s;
       return MOMA_OK;
     };
-    // a full-width job reads its input from an L-plane stage
-    auto staged = [&](const uint32_t* src, const uint32_t** outp) -> int {
-      uint32_t* st = nullptr;
-      int r = alloc(plane_words, &st);
-      if (r) return r;
-      b.copy_in.push_back({st, src, p->n * (uint64_t)f.Ls});
-      b.stage_tops.push_back({st, p->n, f.Ls, f.L});
-      *outp = st;
-      return MOMA_OK;
-    };
     if (job.kind == MOMA_JOB_CYCLIC_MUL) {
       uint32_t* sa = nullptr;
       int r = alloc(2 * plane_words, &sa);
-      uint32_t* sb = sa + plane_words;
-      const uint32_t *ina = job.d_in, *inb = job.d_in2;
-      uint32_t* res = job.d_out;
-      if (!r && full) r = staged(job.d_in, &ina);
-      if (!r && full) r = staged(job.d_in2, &inb);
-      if (!r && full) r = alloc(plane_words, &res);
       if (r) return r;
-      add(*p, sched, passes, p->fwd, none, false, ina, nullptr, sa, sa, 0);
-      add(*p, sched, passes, p->fwd, none, false, inb, nullptr, sb, sb, 0);
-      add(*p, sched, passes, p->inv, p->mul_consts, true, sa, sb, res, res, (uint32_t)passes.size());
-      if (full) b.copy_out.push_back({job.d_out, res, p->n * (uint64_t)f.Ls});
+      uint32_t* sb = sa + plane_words;
+      add(*p, sched, passes, p->fwd, none, false, job.d_in, nullptr, sa, sa, 0);
+      add(*p, sched, passes, p->fwd, none, false, job.d_in2, nullptr, sb, sb, 0);
+      add(*p, sched, passes, p->inv, p->mul_consts, true, sa, sb, job.d_out, job.d_out, (uint32_t)passes.size());
       if (f.Ls > f.L) b.fills.push_back({job.d_out, p->n, f.L, f.Ls});
       continue;
     }
     const bool inverse = job.kind == MOMA_JOB_INVERSE;
-    const uint32_t* in = job.d_in;
-    uint32_t* res = job.d_out;
-    uint32_t* first_out = nullptr;
-    if (full) {
-      int r = staged(job.d_in, &in);
-      if (!r) r = alloc(plane_words, &res);
-      if (r) return r;
-      b.copy_out.push_back({job.d_out, res, p->n * (uint64_t)f.Ls});
-    }
-    first_out = res;
-    if (passes.size() > 1 && in == res) {
+    uint32_t* first_out = job.d_out;
+    if (passes.size() > 1 && job.d_in == job.d_out) {
       int r = alloc(plane_words, &first_out);
       if (r) return r;
     }
-    add(*p, sched, passes, inverse ? p->inv : p->fwd, inverse ? p->inv_consts : none, inverse, in, nullptr,
-        first_out, res, 0);
+    add(*p, sched, passes, inverse ? p->inv : p->fwd, inverse ? p->inv_consts : none, inverse, job.d_in, nullptr,
+        first_out, job.d_out, 0);
     if (f.Ls > f.L && job.d_out != job.d_in) b.fills.push_back({job.d_out, p->n, f.L, f.Ls});
   }
   // upload tables and build the launch list, phase by phase
@@ -316,6 +283,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       bl.L = L;
       bl.mul = std::get<3>(kv.first);
       bl.variant = std::get<5>(kv.first);
+      bl.fw = std::get<6>(kv.first);
       bl.radix_log = std::get<1>(kv.first);
       bl.threads = std::get<2>(kv.first);
       bl.lds = kv.second.lds[ph];
@@ -335,6 +303,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     bl.op = std::get<0>(kv.first);
     bl.L = std::get<1>(kv.first);
     bl.variant = std::get<2>(kv.first);
+    bl.fw = std::get<3>(kv.first);
     bl.nitems = (uint32_t)g.items.size();
     void *dr = nullptr, *dc = nullptr, *di = nullptr;
     int rc = dev_upload(b, g.recs.data(), g.recs.size() * sizeof(BlasJobRec), &dr);
@@ -347,39 +316,24 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     b.blas.push_back(bl);
     b.items += bl.nitems;
   }
-  for (const BatchLaunch& bl : b.launches) ntt_batch_prepare(bl.L, bl.radix_log, bl.lds);
+  for (const BatchLaunch& bl : b.launches) ntt_batch_prepare(bl.L, bl.radix_log, bl.fw, bl.lds);
   // capture the launches into one graph
   if (hipStreamCreate(&b.cap)) return hip_fail(1, "batch stream");
   if (hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal)) return hip_fail(1, "begin capture");
   int err = 0;
   for (const BlasLaunch& bl : b.blas) {
-    err = launch_blas_batch(bl.op, bl.L, bl.variant, bl.d_recs, bl.d_consts, bl.d_items, bl.nitems, b.cap);
+    err = launch_blas_batch(bl.op, bl.L, bl.variant, bl.fw, bl.d_recs, bl.d_consts, bl.d_items, bl.nitems, b.cap);
     if (err) break;
   }
-  for (const PlaneCopy& c : b.copy_in) {
-    if (err) break;
-    err = launch_copy_words(c.dst, c.src, c.words, b.cap);
-    if (err) break;
-  }
-  if (!err)
-    for (const ZeroFill& z : b.stage_tops) {
-      err = launch_zero_planes(z.out, z.n, z.from, z.to, b.cap);
-      if (err) break;
-    }
   for (const BatchLaunch& bl : b.launches) {
     if (err) break;
-    err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.variant, bl.threads, bl.lds, bl.grid, bl.d_passes, bl.d_consts,
-                           bl.d_items, bl.nitems, b.cap);
+    err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.variant, bl.fw, bl.threads, bl.lds, bl.grid, bl.d_passes,
+                           bl.d_consts, bl.d_items, bl.nitems, b.cap);
     if (err) break;
   }
   if (!err)
     for (const ZeroFill& z : b.fills) {
       err = launch_zero_planes(z.out, z.n, z.from, z.to, b.cap);
-      if (err) break;
-    }
-  if (!err)
-    for (const PlaneCopy& c : b.copy_out) {
-      err = launch_copy_words(c.dst, c.src, c.words, b.cap);
       if (err) break;
     }
   hipError_t ec = hipStreamEndCapture(b.cap, &b.graph);
@@ -428,8 +382,7 @@ int moma_batch_run(moma_batch_t b, void* stream) {
 int moma_batch_info(moma_batch_t b, uint32_t* launches, uint64_t* items) {
   if (!b) return set_error(MOMA_E_ARG, "batch is NULL");
   if (launches)
-    *launches = (uint32_t)(b->impl.launches.size() + b->impl.blas.size() + b->impl.fills.size() +
-                           b->impl.copy_in.size() + b->impl.stage_tops.size() + b->impl.copy_out.size());
+    *launches = (uint32_t)(b->impl.launches.size() + b->impl.blas.size() + b->impl.fills.size());
   if (items) *items = b->impl.items;
   return MOMA_OK;
 }

@@ -18,69 +18,102 @@ struct BlasC {
   u32 qinv;
   BarrettC<L> bc;
   u32 alpha_m[L];
-  u32 ls;
+  u32 r2[L];  // 2^(64L) mod q (full-width vmul)
 };
+
+// One element's operation.  A full-width modulus (FW: no headroom for Barrett's
+// pre-scaled modulus) multiplies by Montgomery products that keep the carry
+// out of the top limb: vmul = mont(mont(a, b), 2^(64L) mod q).
+template <int L, int OP, bool KARA, bool FW>
+__device__ __forceinline__ void blas_elem(u32* r, const u32* a, const u32* b, const BlasC<L>& c) {
+  if constexpr (FW) {
+    u32 qv[L];
+    to_vgprs<L>(qv, c.q);
+    if constexpr (OP == OP_VADD) {
+      mod_add_fw<L>(r, a, b, qv);
+    } else if constexpr (OP == OP_VSUB) {
+      mod_sub_v<L>(r, a, b, qv);
+    } else if constexpr (OP == OP_VMUL) {
+      u32 t[L], r2v[L];
+      mont_mul_fw<L>(t, a, b, c.q, c.qinv, qv);    // a b 2^(-32L)
+      to_vgprs<L>(r2v, c.r2);
+      mont_mul_fw<L>(r, t, r2v, c.q, c.qinv, qv);  // times 2^(64L) 2^(-32L)
+    } else {
+      u32 t[L], av[L];
+      to_vgprs<L>(av, c.alpha_m);
+      mont_mul_fw<L>(t, a, av, c.q, c.qinv, qv);   // alpha * x
+      mod_add_fw<L>(r, t, b, qv);                  // + y
+    }
+  } else {
+    if constexpr (OP == OP_VADD) {
+      mod_add<L>(r, a, b, c.q);
+    } else if constexpr (OP == OP_VSUB) {
+      mod_sub<L>(r, a, b, c.q);
+    } else if constexpr (OP == OP_VMUL) {
+      barrett_mul<L, KARA>(r, a, b, c.bc);
+    } else {
+      u32 t[L];
+      mont_mul<L>(t, a, c.alpha_m, c.q, c.qinv);  // alpha * x
+      mod_add<L>(r, t, b, c.q);                   // + y
+    }
+  }
+}
 
 // One element per lane.  Every word is streamed once, so loads and stores are
 // nontemporal (no reuse to keep in the caches).  Four elements per lane with
 // 16-byte accesses was measured at n = 2^24: vadd at 256 bits took 333 us
 // against 280 us with one element per lane.
-template <int L, int OP, bool KARA>
+template <int L, int OP, bool KARA, bool FW>
 __global__ __launch_bounds__(256) void blas_kernel(const u32* __restrict__ pa, const u32* __restrict__ pb,
                                                    u32* __restrict__ pout, u64 n, BlasC<L> c) {
   const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  // a full-width modulus has one storage plane fewer than compute limbs: the
-  // missing top limb of every input is zero, and the result's is zero too
-  const int lim = c.ls < (u32)L ? (int)c.ls : L;
   u32 a[L], b[L], r[L];
 #pragma unroll
   for (int j = 0; j < L; j++) {
-    a[j] = j < lim ? __builtin_nontemporal_load(pa + (u64)j * n + i) : 0u;
-    b[j] = j < lim ? __builtin_nontemporal_load(pb + (u64)j * n + i) : 0u;
+    a[j] = __builtin_nontemporal_load(pa + (u64)j * n + i);
+    b[j] = __builtin_nontemporal_load(pb + (u64)j * n + i);
   }
-  if (OP == OP_VADD) {
-    mod_add<L>(r, a, b, c.q);
-  } else if (OP == OP_VSUB) {
-    mod_sub<L>(r, a, b, c.q);
-  } else if (OP == OP_VMUL) {
-    barrett_mul<L, KARA>(r, a, b, c.bc);
-  } else {
-    u32 t[L];
-    mont_mul<L>(t, a, c.alpha_m, c.q, c.qinv);  // alpha * x
-    mod_add<L>(r, t, b, c.q);                   // + y
-  }
+  blas_elem<L, OP, KARA, FW>(r, a, b, c);
 #pragma unroll
-  for (int j = 0; j < L; j++)
-    if (j < lim) __builtin_nontemporal_store(r[j], pout + (u64)j * n + i);
+  for (int j = 0; j < L; j++) __builtin_nontemporal_store(r[j], pout + (u64)j * n + i);
 }
 
-template <int L, int OP, bool KARA>
+template <int L, int OP, bool KARA, bool FW>
 static int launch_blas_LK(const BlasArgs& a, const BlasC<L>& c, hipStream_t s) {
   const unsigned T = 256;
   const u64 blocks = (a.n + T - 1) / T;
-  hipLaunchKernelGGL((blas_kernel<L, OP, KARA>), dim3((unsigned)blocks), dim3(T), 0, s, a.a, a.b, a.out, a.n, c);
+  hipLaunchKernelGGL((blas_kernel<L, OP, KARA, FW>), dim3((unsigned)blocks), dim3(T), 0, s, a.a, a.b, a.out, a.n,
+                     c);
   return (int)hipGetLastError();
 }
 
-// mont_mul takes its second operand from VGPRs; alpha is uniform, so keep a
-// copy per lane (cheap: L moves per element).
-template <int L, int OP>
-static int launch_blas_L(const FieldRaw& f, const BlasArgs& a, hipStream_t s) {
+template <int L>
+static BlasC<L> blas_consts(const FieldRaw& f, const BlasArgs& a) {
   BlasC<L> c;
+  memset(&c, 0, sizeof(c));
   for (int j = 0; j < L; j++) {
     c.q[j] = f.q[j];
     c.bc.qn[j] = f.qn[j];
     c.bc.mu[j] = f.mu[j];
     c.alpha_m[j] = a.alpha_m[j];
+    c.r2[j] = f.r2[j];
   }
   c.qinv = f.qinv;
   c.bc.d = f.d;
-  c.ls = a.ls;
+  return c;
+}
+
+// A full-width modulus runs the Montgomery products (the product variant is a
+// choice of Barrett's products and does not apply).
+template <int L, int OP>
+static int launch_blas_L(const FieldRaw& f, const BlasArgs& a, hipStream_t s) {
+  BlasC<L> c = blas_consts<L>(f, a);
+  if (f.fw) return launch_blas_LK<L, OP, false, true>(a, c, s);
   if constexpr (OP == OP_VMUL && L >= 2) {
-    if (a.variant == 1) return launch_blas_LK<L, OP, true>(a, c, s);
+    if (a.variant == 1) return launch_blas_LK<L, OP, true, false>(a, c, s);
   }
-  return launch_blas_LK<L, OP, false>(a, c, s);
+  return launch_blas_LK<L, OP, false, false>(a, c, s);
 }
 
 template <int L>
@@ -112,7 +145,7 @@ int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s) {
 // carries its own vectors, length and modulus constants.  Items are ordered
 // job by job, so the blocks of a vector stay together.
 
-template <int L, int OP, bool KARA>
+template <int L, int OP, bool KARA, bool FW>
 __global__ __launch_bounds__(256) void blas_batch_kernel(const BlasJobRec* __restrict__ recs,
                                                          const BlasC<L>* __restrict__ consts,
                                                          const uint2* __restrict__ items, u32 nitems) {
@@ -124,43 +157,15 @@ __global__ __launch_bounds__(256) void blas_batch_kernel(const BlasJobRec* __res
   const u64 i = (u64)it.y * blockDim.x + threadIdx.x;
   if (i >= r.n) return;
   const u64 n = r.n;
-  const int lim = c.ls < (u32)L ? (int)c.ls : L;
   u32 a[L], bb[L], res[L];
 #pragma unroll
   for (int j = 0; j < L; j++) {
-    a[j] = j < lim ? r.a[(u64)j * n + i] : 0u;
-    bb[j] = j < lim ? r.b[(u64)j * n + i] : 0u;
+    a[j] = r.a[(u64)j * n + i];
+    bb[j] = r.b[(u64)j * n + i];
   }
-  if (OP == OP_VADD) {
-    mod_add<L>(res, a, bb, c.q);
-  } else if (OP == OP_VSUB) {
-    mod_sub<L>(res, a, bb, c.q);
-  } else if (OP == OP_VMUL) {
-    barrett_mul<L, KARA>(res, a, bb, c.bc);
-  } else {
-    u32 t[L];
-    mont_mul<L>(t, a, c.alpha_m, c.q, c.qinv);
-    mod_add<L>(res, t, bb, c.q);
-  }
+  blas_elem<L, OP, KARA, FW>(res, a, bb, c);
 #pragma unroll
-  for (int j = 0; j < L; j++)
-    if (j < lim) r.out[(u64)j * n + i] = res[j];
-}
-
-template <int L>
-static BlasC<L> blas_consts(const FieldRaw& f, const BlasArgs& a) {
-  BlasC<L> c;
-  memset(&c, 0, sizeof(c));
-  for (int j = 0; j < L; j++) {
-    c.q[j] = f.q[j];
-    c.bc.qn[j] = f.qn[j];
-    c.bc.mu[j] = f.mu[j];
-    c.alpha_m[j] = a.alpha_m[j];
-  }
-  c.qinv = f.qinv;
-  c.bc.d = f.d;
-  c.ls = a.ls;
-  return c;
+  for (int j = 0; j < L; j++) r.out[(u64)j * n + i] = res[j];
 }
 
 size_t blas_consts_bytes(int L) {
@@ -186,17 +191,26 @@ void blas_fill_consts(const FieldRaw& f, const BlasArgs& a, void* dst) {
   }
 }
 
-template <int L, int OP, bool KARA>
+template <int L, int OP, bool KARA, bool FW = false>
 static int launch_blas_batch_LOK(const void* recs, const void* consts, const uint2* items, uint32_t nitems,
                                  hipStream_t s) {
-  hipLaunchKernelGGL((blas_batch_kernel<L, OP, KARA>), dim3(nitems), dim3(256), 0, s, (const BlasJobRec*)recs,
+  hipLaunchKernelGGL((blas_batch_kernel<L, OP, KARA, FW>), dim3(nitems), dim3(256), 0, s, (const BlasJobRec*)recs,
                      (const BlasC<L>*)consts, items, nitems);
   return (int)hipGetLastError();
 }
 
 template <int L>
-static int launch_blas_batch_L(int op, uint32_t variant, const void* recs, const void* consts, const uint2* items,
-                               uint32_t nitems, hipStream_t s) {
+static int launch_blas_batch_L(int op, uint32_t variant, bool fw, const void* recs, const void* consts,
+                               const uint2* items, uint32_t nitems, hipStream_t s) {
+  if (fw) {
+    switch (op) {
+      case OP_VADD: return launch_blas_batch_LOK<L, OP_VADD, false, true>(recs, consts, items, nitems, s);
+      case OP_VSUB: return launch_blas_batch_LOK<L, OP_VSUB, false, true>(recs, consts, items, nitems, s);
+      case OP_VMUL: return launch_blas_batch_LOK<L, OP_VMUL, false, true>(recs, consts, items, nitems, s);
+      case OP_AXPY: return launch_blas_batch_LOK<L, OP_AXPY, false, true>(recs, consts, items, nitems, s);
+    }
+    return (int)hipErrorInvalidValue;
+  }
   switch (op) {
     case OP_VADD: return launch_blas_batch_LOK<L, OP_VADD, false>(recs, consts, items, nitems, s);
     case OP_VSUB: return launch_blas_batch_LOK<L, OP_VSUB, false>(recs, consts, items, nitems, s);
@@ -210,12 +224,12 @@ static int launch_blas_batch_L(int op, uint32_t variant, const void* recs, const
   return (int)hipErrorInvalidValue;
 }
 
-int launch_blas_batch(int op, int L, uint32_t variant, const void* recs, const void* consts, const uint2* items,
-                      uint32_t nitems, hipStream_t s) {
+int launch_blas_batch(int op, int L, uint32_t variant, bool fw, const void* recs, const void* consts,
+                      const uint2* items, uint32_t nitems, hipStream_t s) {
   if (nitems == 0) return 0;
   switch (L) {
 #define CASE(LL) \
-  case LL: return launch_blas_batch_L<LL>(op, variant, recs, consts, items, nitems, s);
+  case LL: return launch_blas_batch_L<LL>(op, variant, fw, recs, consts, items, nitems, s);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }
@@ -262,18 +276,6 @@ int launch_fill_residues(uint32_t* p, uint64_t n, int planes, int top, uint32_t 
   if (count == 0) return 0;
   hipLaunchKernelGGL(fill_residues_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, n, planes, top,
                      top_mask, seed);
-  return (int)hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void copy_words_kernel(u32* __restrict__ dst, const u32* __restrict__ src, u64 count) {
-  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) dst[i] = src[i];
-}
-
-int launch_copy_words(uint32_t* dst, const uint32_t* src, uint64_t count, hipStream_t s) {
-  if (count == 0) return 0;
-  u64 blocks = (count + 255) / 256;
-  hipLaunchKernelGGL(copy_words_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, count);
   return (int)hipGetLastError();
 }
 

@@ -37,8 +37,8 @@ std::mutex g_mu;
 static std::map<std::vector<uint32_t>, std::shared_ptr<FieldEntry>> g_fields;
 
 // v (< 2^(bD)) as the D b-bit digits of the transform's digit form
-static void digits_of(const HBig& v, int L, uint32_t* out) {
-  int b = digit_bits(L), D = digit_count(L);
+static void digits_of(const HBig& v, int L, bool fw, uint32_t* out) {
+  int b = digit_bits(L), D = digit_count(L, fw);
   for (int i = 0; i < D; i++) {
     uint32_t w[2] = {0, 0};
     HBig::shr(v, b * i).to_limbs(w, 2);
@@ -67,33 +67,37 @@ int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* 
   if (M > 32 * (int)limbs)
     return set_error(MOMA_E_MODULUS, "bitlen(q) = " + std::to_string(M) + " exceeds 32*limbs = " +
                                          std::to_string(32 * limbs));
-  // compute limbs keep 4 bits of headroom for the lazy reductions; a modulus
-  // within 4 bits of the storage width (full width) computes in one more limb
-  if ((M + 4 + 31) / 32 > kMaxLimbs)
-    return set_error(MOMA_E_UNSUPPORTED, "a modulus of " + std::to_string(M) + " bits needs " +
-                                             std::to_string((M + 4 + 31) / 32) + " compute limbs (at most 32)");
   FieldRaw& f = fe->f;
   memset(&f, 0, sizeof(f));
+  // compute limbs keep 4 bits of headroom for the lazy reductions and
+  // Barrett's pre-scaled modulus; a modulus within 4 bits of the storage
+  // width (full width) computes in the storage limbs with canonical operands
+  // and Montgomery products that carry out of the top limb
   f.L = (M + 4 + 31) / 32;
+  f.fw = f.L > (int)limbs ? 1 : 0;
+  if (f.fw) f.L = (int)limbs;
   f.Ls = (int)limbs;
   Q.to_limbs(f.q, kMaxLimbs);
   f.qinv = neg_inv32(f.q[0]);
   HBig one_m = HBig::mod(HBig::pow2(32 * f.L), Q);
   one_m.to_limbs(f.one_m, kMaxLimbs);
-  int Mn = 32 * f.L - 4;
-  f.d = (uint32_t)(Mn - M);
-  HBig qn = HBig::shl(Q, (int)f.d);
-  qn.to_limbs(f.qn, kMaxLimbs);
-  HBig mu;
-  HBig::divmod(HBig::pow2(2 * Mn + 3), qn, &mu, nullptr);
-  if (mu.bitlen() > 32 * f.L) return set_error(MOMA_E_MODULUS, "internal: Barrett constant too wide");
-  mu.to_limbs(f.mu, kMaxLimbs);
+  HBig::mod(HBig::pow2(64 * f.L), Q).to_limbs(f.r2, kMaxLimbs);
+  if (!f.fw) {
+    int Mn = 32 * f.L - 4;
+    f.d = (uint32_t)(Mn - M);
+    HBig qn = HBig::shl(Q, (int)f.d);
+    qn.to_limbs(f.qn, kMaxLimbs);
+    HBig mu;
+    HBig::divmod(HBig::pow2(2 * Mn + 3), qn, &mu, nullptr);
+    if (mu.bitlen() > 32 * f.L) return set_error(MOMA_E_MODULUS, "internal: Barrett constant too wide");
+    mu.to_limbs(f.mu, kMaxLimbs);
+  }
   // digit form of the transform's twiddle multiply
   {
     DigitConsts& dc = fe->dc;
     memset(&dc, 0, sizeof(dc));
-    int b = digit_bits(f.L), D = digit_count(f.L);
-    digits_of(Q, f.L, dc.qd);
+    int b = digit_bits(f.L), D = digit_count(f.L, f.fw);
+    digits_of(Q, f.L, f.fw, dc.qd);
     dc.qinvd = f.qinv & ((1u << b) - 1);
     fe->adj = HBig::mod(HBig::pow2(b * D), Q);
     fe->adj.to_limbs(dc.adj, kMaxLimbs);
@@ -115,17 +119,17 @@ int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* 
 
 static std::map<std::vector<uint32_t>, std::shared_ptr<NttPlan>> g_plans;
 
-uint32_t max_radix_log(int L) {
-  if (L <= kMaxLimbsRadix16) return 4u;
-  return L <= kMaxLimbsRadix8 ? 3u : (L <= kMaxLimbsRadix4 ? 2u : 1u);
+uint32_t max_radix_log(int L, bool fw) {
+  uint32_t r = L <= kMaxLimbsRadix16 ? 4u : (L <= kMaxLimbsRadix8 ? 3u : (L <= kMaxLimbsRadix4 ? 2u : 1u));
+  return fw ? std::min(r, L <= kMaxLimbsRadix4Fw ? 2u : 1u) : r;
 }
 
 // Split log2 n stages into passes for a schedule; returns MOMA_OK or an error
 // code when the schedule cannot run this size.
-int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out) {
+int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out, bool fw) {
   if (s.threads < 64 || s.threads > 1024 || s.threads % 64)
     return set_error(MOMA_E_ARG, "threads must be a multiple of 64 in [64, 1024]");
-  if (s.radix_log < 1 || s.radix_log > max_radix_log(L))
+  if (s.radix_log < 1 || s.radix_log > max_radix_log(L, fw))
     return set_error(MOMA_E_UNSUPPORTED, "radix_log out of range for this limb count");
   if (s.threads > ntt_max_threads(L, s.radix_log))
     return set_error(MOMA_E_UNSUPPORTED, "too many threads for this limb count and radix");
@@ -210,12 +214,12 @@ NttSchedule batch_schedule(int L, uint32_t logn) {
   return first_feasible(L, logn, shapes);
 }
 
-NttSchedule initial_schedule(int L, uint32_t logn) {
+NttSchedule initial_schedule(int L, uint32_t logn, bool fw) {
   std::string keep = g_detail;
   NttSchedule s;
   std::vector<NttPass> ps;
-  bool ok = tune_db_best(current_device_name(), L, logn, &s) && plan_passes(L, logn, s, &ps) == MOMA_OK;
-  if (!ok) ok = costmodel_pick(L, logn, &s) && plan_passes(L, logn, s, &ps) == MOMA_OK;
+  bool ok = tune_db_best(current_device_name(), L, logn, &s) && plan_passes(L, logn, s, &ps, fw) == MOMA_OK;
+  if (!ok) ok = costmodel_pick(L, logn, &s) && plan_passes(L, logn, s, &ps, fw) == MOMA_OK;
   if (!ok) s = default_schedule(L, logn);
   g_detail = keep;
   return s;
@@ -268,7 +272,7 @@ static int build_tables(NttPlan& p, const HBig& w, DirTables* t) {
   for (int j = 0; j < L; j++) lad[(size_t)(p.logn + 1) * L + j] = p.fe->dc.adj[j];
   int e = upload(&t->ladder, lad);
   if (e) return hip_fail(e, "ladder upload");
-  e = (int)hipMalloc((void**)&t->tw, (size_t)p.n * digit_stride(L) * sizeof(uint32_t));
+  e = (int)hipMalloc((void**)&t->tw, (size_t)p.n * digit_stride(L, f.fw) * sizeof(uint32_t));
   if (e) {
     t->tw = nullptr;
     free_tables(t);
@@ -343,8 +347,8 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   p->n = n;
   p->logn = 0;
   while ((1ull << p->logn) < n) p->logn++;
-  p->sched = initial_schedule(fe->f.L, p->logn);
-  rc = plan_passes(fe->f.L, p->logn, p->sched, &p->passes);
+  p->sched = initial_schedule(fe->f.L, p->logn, fe->f.fw);
+  rc = plan_passes(fe->f.L, p->logn, p->sched, &p->passes, fe->f.fw);
   if (rc) return rc;
   if (check_planes(*p)) return set_error(MOMA_E_UNSUPPORTED, "no valid pass split for this size");
   HBig Winv = HBig::powmod(W, HBig(n - 1), Q);
@@ -355,9 +359,9 @@ int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limb
   const HBig& rd = fe->adj;
   HBig nscale = HBig::mulmod(ninv, rd, Q);
   memset(&p->inv_consts, 0, sizeof(p->inv_consts));
-  digits_of(nscale, fe->f.L, p->inv_consts.nscale_d);
+  digits_of(nscale, fe->f.L, fe->f.fw, p->inv_consts.nscale_d);
   memset(&p->mul_consts, 0, sizeof(p->mul_consts));
-  digits_of(HBig::mulmod(nscale, rd, Q), fe->f.L, p->mul_consts.nscale_d);
+  digits_of(HBig::mulmod(nscale, rd, Q), fe->f.L, fe->f.fw, p->mul_consts.nscale_d);
   rc = build_tables(*p, W, &p->fwd);
   if (rc) return rc;
   rc = build_tables(*p, Winv, &p->inv);
@@ -427,32 +431,16 @@ static int plan_buffer(NttPlan& p, uint32_t** slot, size_t copies, const char* w
   return MOMA_OK;
 }
 
-// Full-width modulus (Ls = L - 1 storage planes): copy the Ls planes of src
-// into stage and zero its top plane, so the kernels read L planes.
-static int stage_in(NttPlan& p, uint32_t* stage, const uint32_t* src, hipStream_t s) {
-  const FieldRaw& f = p.fe->f;
-  int e = launch_copy_words(stage, src, p.n * (uint64_t)f.Ls, s);
-  if (!e) e = launch_zero_planes(stage, p.n, f.Ls, f.L, s);
-  return e ? hip_fail(e, "full-width staging") : MOMA_OK;
-}
-
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s) {
   const FieldRaw& f = p.fe->f;
-  const bool full = f.Ls < f.L;
   std::vector<NttPass> passes;
   NttSchedule sched;
   uint32_t* first_out = d_out;
-  uint32_t* stage = nullptr;
   {
     std::lock_guard<std::mutex> lk(p.mu);
     passes = p.passes;
     sched = p.sched;
-    if (full) {
-      int rc = plan_buffer(p, &p.stage, 1, "staging");
-      if (rc) return rc;
-      stage = p.stage;
-    }
-    if (passes.size() > 1 && (full || d_in == d_out)) {
+    if (passes.size() > 1 && d_in == d_out) {
       int rc = plan_buffer(p, &p.scratch, 1, "scratch");
       if (rc) return rc;
       first_out = p.scratch;
@@ -462,15 +450,6 @@ int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hi
   memset(&none, 0, sizeof(none));
   const DirTables& t = inverse ? p.inv : p.fwd;
   const NttConsts& nc = inverse ? p.inv_consts : none;
-  if (full) {
-    // through L planes in place on the stage, then back to the caller's Ls planes
-    int rc = stage_in(p, stage, d_in, s);
-    if (!rc) rc = enqueue_passes(p, passes, sched, t, nc, inverse, stage, nullptr,
-                                 passes.size() > 1 ? first_out : stage, stage, s);
-    if (rc) return rc;
-    int e = launch_copy_words(d_out, stage, p.n * (uint64_t)f.Ls, s);
-    return e ? hip_fail(e, "full-width staging") : MOMA_OK;
-  }
   int rc = enqueue_passes(p, passes, sched, t, nc, inverse, d_in, nullptr, first_out, d_out, s);
   if (rc) return rc;
   if (f.Ls > f.L && d_out != d_in) {
@@ -484,51 +463,29 @@ int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hi
 // plan's spectra buffer, and the inverse transform's first pass multiplies
 // them pointwise while loading (digit-form Montgomery, a factor 2^(-bD)); its
 // last pass scales by n^-1 2^(bD), which cancels that factor.
-uint64_t cyclic_mul_scratch_words(const NttPlan& p) {
-  const FieldRaw& f = p.fe->f;
-  return (uint64_t)(f.Ls < f.L ? 3 : 2) * p.n * (uint64_t)f.L;
-}
+uint64_t cyclic_mul_scratch_words(const NttPlan& p) { return 2ull * p.n * (uint64_t)p.fe->f.L; }
 
 int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s,
                    uint32_t* ext) {
   const FieldRaw& f = p.fe->f;
-  const bool full = f.Ls < f.L;
   std::vector<NttPass> passes;
   NttSchedule sched;
-  uint32_t *spec = nullptr, *stage = nullptr;
+  uint32_t* spec = ext;  // caller-provided scratch: [spectrum a | spectrum b]
   {
     std::lock_guard<std::mutex> lk(p.mu);
     passes = p.passes;
     sched = p.sched;
-    if (ext) {
-      // caller-provided scratch: [spectrum a | spectrum b | stage (full width)]
-      spec = ext;
-      stage = ext + 2 * (size_t)p.n * f.L;
-    } else {
+    if (!ext) {
       int rc = plan_buffer(p, &p.spectra, 2, "spectra");
-      if (!rc && full) rc = plan_buffer(p, &p.stage, 1, "staging");
       if (rc) return rc;
       spec = p.spectra;
-      stage = p.stage;
     }
   }
   uint32_t* sa = spec;
   uint32_t* sb = spec + (size_t)p.n * f.L;
   NttConsts none;
   memset(&none, 0, sizeof(none));
-  int rc = MOMA_OK;
-  if (full) {
-    // each input through the stage into its spectrum; the product back through the stage
-    rc = stage_in(p, stage, d_a, s);
-    if (!rc) rc = enqueue_passes(p, passes, sched, p.fwd, none, false, stage, nullptr, sa, sa, s);
-    if (!rc) rc = stage_in(p, stage, d_b, s);
-    if (!rc) rc = enqueue_passes(p, passes, sched, p.fwd, none, false, stage, nullptr, sb, sb, s);
-    if (!rc) rc = enqueue_passes(p, passes, sched, p.inv, p.mul_consts, true, sa, sb, stage, stage, s);
-    if (rc) return rc;
-    int e = launch_copy_words(d_out, stage, p.n * (uint64_t)f.Ls, s);
-    return e ? hip_fail(e, "full-width staging") : MOMA_OK;
-  }
-  rc = enqueue_passes(p, passes, sched, p.fwd, none, false, d_a, nullptr, sa, sa, s);
+  int rc = enqueue_passes(p, passes, sched, p.fwd, none, false, d_a, nullptr, sa, sa, s);
   if (!rc) rc = enqueue_passes(p, passes, sched, p.fwd, none, false, d_b, nullptr, sb, sb, s);
   if (!rc) rc = enqueue_passes(p, passes, sched, p.inv, p.mul_consts, true, sa, sb, d_out, d_out, s);
   if (rc) return rc;
@@ -877,9 +834,9 @@ int moma_ntt_set_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, 
   int rc = get_plan(q, omega, n, limbs, &p);
   if (rc) return rc;
   NttSchedule s = sched ? NttSchedule{sched->tile_log, sched->col_log, sched->threads, sched->radix_log}
-                        : initial_schedule(p->fe->f.L, p->logn);
+                        : initial_schedule(p->fe->f.L, p->logn, p->fe->f.fw);
   std::vector<NttPass> ps;
-  rc = plan_passes(p->fe->f.L, p->logn, s, &ps);
+  rc = plan_passes(p->fe->f.L, p->logn, s, &ps, p->fe->f.fw);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(p->mu);
   p->sched = s;

@@ -11,26 +11,37 @@ constexpr int kMaxLimbs = 32;
 // Digit form of the transform's twiddle multiply: b-bit digits (b = 29, or 28
 // above 28 limbs), D of them, so that 2D products of two digits plus a carry
 // stay below 2^64 and b*D >= 32L - 2 covers every operand below 4q.
+// A full-width modulus (fw: bitlen(q) > 32L - 4) keeps canonical operands
+// below q < 2^(32L), so its digits cover 32L bits.
 constexpr int digit_bits(int L) { return L <= 28 ? 29 : 28; }
-constexpr int digit_count(int L) { return (32 * L - 2 + digit_bits(L) - 1) / digit_bits(L); }
-constexpr int digit_stride(int L) { return digit_count(L) + (digit_count(L) & 1); }  // table words per entry
+constexpr int digit_count(int L, bool fw = false) {
+  return (32 * L - (fw ? 0 : 2) + digit_bits(L) - 1) / digit_bits(L);
+}
+constexpr int digit_stride(int L, bool fw = false) {  // table words per entry
+  return digit_count(L, fw) + (digit_count(L, fw) & 1);
+}
 
 // widest limb counts that get radix-4 / radix-8 / radix-16 register units
 constexpr int kMaxLimbsRadix4 = 10;
 constexpr int kMaxLimbsRadix8 = 5;
 constexpr int kMaxLimbsRadix16 = 2;
+// full-width moduli: radix-4 units up to 9 limbs (at 10 the digit multiply
+// takes one digit more and the unit no longer fits the register budget)
+constexpr int kMaxLimbsRadix4Fw = 9;
 
 // Constants of one modulus, sized for the largest limb count; the launchers copy
 // the first L words of each array into a compile-time sized kernel argument.
 struct FieldRaw {
-  int L;                   // compute limbs: ceil((bitlen(q) + 4) / 32)
-  int Ls;                  // storage limbs (planes) given by the caller; L - 1 for a full-width q
+  int L;                   // compute limbs: ceil((bitlen(q) + 4) / 32), or the storage limbs for a full-width q
+  int Ls;                  // storage limbs (planes) given by the caller, >= L
+  int fw;                  // full width: bitlen(q) > 32 L - 4, no headroom for lazy reduction
   uint32_t q[kMaxLimbs];
   uint32_t qinv;           // -q^{-1} mod 2^32 (Montgomery)
   uint32_t one_m[kMaxLimbs];  // 2^(32L) mod q (1 in Montgomery form)
   uint32_t qn[kMaxLimbs];  // q * 2^d, bitlen 32L - 4 (Barrett)
   uint32_t mu[kMaxLimbs];  // floor(2^(2(32L-4)+3) / qn)
   uint32_t d;              // Barrett pre-scale shift
+  uint32_t r2[kMaxLimbs];  // 2^(64L) mod q: full-width vmul (two Montgomery products)
 };
 
 enum BlasOp { OP_VADD = 0, OP_VSUB = 1, OP_VMUL = 2, OP_AXPY = 3 };
@@ -42,7 +53,7 @@ struct BlasArgs {
   uint64_t n;
   uint32_t alpha_m[kMaxLimbs];  // axpy: alpha * 2^(32L) mod q (Montgomery form)
   uint32_t variant;              // vmul: 0 schoolbook products, 1 Karatsuba (L >= 2)
-  uint32_t ls;                   // storage planes; fewer than L for a full-width modulus
+  uint32_t ls;                   // storage planes (>= L; the planes above L are written as zero)
 };
 
 // One pass of the transform: k radix-2 stages [K, K+k) over tiles of C groups.
@@ -78,7 +89,7 @@ struct NttConsts {
 
 // per-modulus constants of the digit-form multiply
 struct DigitConsts {
-  uint32_t qd[40];   // q in b-bit digits
+  uint32_t qd[40];   // q in b-bit digits (digit_count(L, fw) of them)
   uint32_t qinvd;    // -q^{-1} mod 2^b
   uint32_t adj[kMaxLimbs];  // 2^(b*D) mod q, converts a table entry to digit Montgomery form
 };
@@ -89,17 +100,16 @@ int set_error(int code, const std::string& detail);
 // launchers (return hipError_t as int)
 int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s);
 int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, hipStream_t s);
-// dst[i] = src[i] for i < count (a kernel, so that graph capture records no copy node)
-int launch_copy_words(uint32_t* dst, const uint32_t* src, uint64_t count, hipStream_t s);
 int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& c,
                     uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s);
 // batched transforms: one launch runs items (pass record, tile) of many plans
-size_t ntt_consts_bytes(int L);
-void ntt_batch_prepare(int L, uint32_t radix_log, size_t lds);
+// (fw: full-width moduli, whose kernels and constants are of their own kind)
+size_t ntt_consts_bytes(int L, bool fw);
+void ntt_batch_prepare(int L, uint32_t radix_log, bool fw, size_t lds);
 void ntt_fill_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc, void* dst);
-int launch_ntt_batch(int L, uint32_t radix_log, bool mul, bool variant, uint32_t threads, size_t lds, uint32_t grid,
-                     const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
-                     hipStream_t s);
+int launch_ntt_batch(int L, uint32_t radix_log, bool mul, bool variant, bool fw, uint32_t threads, size_t lds,
+                     uint32_t grid, const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items,
+                     uint32_t nitems, hipStream_t s);
 // whether a batch pass record runs the variant kernel (direct first round,
 // cross-lane last stage); sets the record's `direct` flag
 bool ntt_batch_variant(int L, uint32_t radix_log, uint32_t threads, NttPassArgs* a);

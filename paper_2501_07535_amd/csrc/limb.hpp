@@ -234,20 +234,20 @@ __device__ __forceinline__ void mont_mul(u32* r, const u32* a, const u32* b, con
 // one v_mad_u64_u32 into a 64-bit accumulator with no carry handling, which the
 // compiler emits from plain C.  Operands stay in 32-bit limbs everywhere else;
 // the multiply converts on the way in and out.
-template <int L>
+template <int L, bool FW = false>
 struct Digits {
   static constexpr int b = digit_bits(L);
-  static constexpr int D = digit_count(L);
+  static constexpr int D = digit_count(L, FW);
   static constexpr u32 mask = (1u << b) - 1;
 };
 
 // d = y in base 2^b (y < 2^(b*D))
-template <int L>
+template <int L, bool FW = false>
 __device__ __forceinline__ void to_digits(u32* d, const u32* y) {
-  constexpr int b = Digits<L>::b, D = Digits<L>::D;
+  constexpr int b = Digits<L, FW>::b, D = Digits<L, FW>::D;
 #pragma unroll
   for (int i = 0; i < D; i++) {
-    constexpr u32 m = Digits<L>::mask;
+    constexpr u32 m = Digits<L, FW>::mask;
     const int pos = b * i, l = pos / 32, s = pos % 32;
     u32 lo = l < L ? y[l] : 0u, hi = l + 1 < L ? y[l + 1] : 0u;
     u32 v = s ? __builtin_amdgcn_alignbit(hi, lo, s) : lo;
@@ -256,9 +256,9 @@ __device__ __forceinline__ void to_digits(u32* d, const u32* y) {
 }
 
 // y = the value of digits d, as L 32-bit limbs (the value fits 32L bits)
-template <int L>
+template <int L, bool FW = false>
 __device__ __forceinline__ void from_digits(u32* y, const u32* d) {
-  constexpr int b = Digits<L>::b, D = Digits<L>::D;
+  constexpr int b = Digits<L, FW>::b, D = Digits<L, FW>::D;
 #pragma unroll
   for (int j = 0; j < L; j++) {
     const int pos = 32 * j, i = pos / b, s = pos % b;
@@ -269,16 +269,34 @@ __device__ __forceinline__ void from_digits(u32* y, const u32* d) {
   }
 }
 
-// t = y * w * 2^(-bD) mod q in [0, 2q), w given as digits (Montgomery form for
-// R = 2^(bD)), y < 4q in 32-bit limbs.  Product scanning: column i sums every
-// digit product y_j w_{i-j} and m_j q_{i-j}; m_i = (low b bits) * qinvd mod 2^b
-// clears the low b bits, then the column shifts right by b.  2D^2 products.
+// Bit 32L (and above) of the value of digits d, whose last digit may exceed
+// b bits: the carry word of a full-width result below 2q < 2^(32L+1).
 template <int L>
-__device__ __forceinline__ void mont_mul_digits(u32* t, const u32* y, const u32* wd, const u32* qd, u32 qinvd) {
-  constexpr int b = Digits<L>::b, D = Digits<L>::D;
-  constexpr u32 mask = Digits<L>::mask;
+__device__ __forceinline__ u32 top_of_digits(const u32* d) {
+  constexpr int b = Digits<L, true>::b, D = Digits<L, true>::D;
+  constexpr int i = (32 * L) / b, s = (32 * L) % b;
+  if constexpr (i >= D) {
+    return d[D - 1] >> (32 * L - b * (D - 1));  // above the last digit's b bits
+  } else {
+    u32 v = d[i] >> s;
+    if constexpr (i + 1 < D) v |= d[i + 1] << (b - s);
+    return v;
+  }
+}
+
+// t = y * w * 2^(-bD) mod q in [0, 2q), w given as digits (Montgomery form for
+// R = 2^(bD)), y < 4q in 32-bit limbs (y < q for a full-width modulus, FW).
+// Product scanning: column i sums every digit product y_j w_{i-j} and
+// m_j q_{i-j}; m_i = (low b bits) * qinvd mod 2^b clears the low b bits, then
+// the column shifts right by b.  2D^2 products.  FW: the result may reach
+// 2^(32L); *top receives its bit 32L (0 or 1).
+template <int L, bool FW = false>
+__device__ __forceinline__ void mont_mul_digits(u32* t, const u32* y, const u32* wd, const u32* qd, u32 qinvd,
+                                                u32* top = nullptr) {
+  constexpr int b = Digits<L, FW>::b, D = Digits<L, FW>::D;
+  constexpr u32 mask = Digits<L, FW>::mask;
   u32 a[D], m[D], r[D];
-  to_digits<L>(a, y);
+  to_digits<L, FW>(a, y);
   u64 acc = 0;
 #pragma unroll
   for (int i = 0; i < D; i++) {
@@ -298,7 +316,115 @@ __device__ __forceinline__ void mont_mul_digits(u32* t, const u32* y, const u32*
     acc >>= b;
   }
   r[D - 1] = (u32)acc;
-  from_digits<L>(t, r);
+  from_digits<L, FW>(t, r);
+  if constexpr (FW) *top = top_of_digits<L>(r);
+}
+
+// ----------------------------------------------------------------- full width
+//
+// A full-width modulus (bitlen(q) > 32L - 4) leaves no headroom for the lazy
+// reductions: operands stay canonical in [0, q), and a sum or a Montgomery
+// product below 2q can carry out of the top limb, so that bit travels in a
+// word of its own beside the L limbs (Section 5.2 names Montgomery
+// multiplication for such moduli).
+
+// r = (top 2^(32L) + t) mod q for a value below 2q (top in {0, 1}): the
+// (L+1)-word trial subtraction's final borrow says whether the value is < q.
+template <int L>
+__device__ __forceinline__ void reduce_top(u32* r, const u32* t, u32 top, const u32* qv) {
+  u32 d[L], dt;
+  u64 br = sub_vv<L>(d, t, qv);
+  asm("v_subb_co_u32 %0, %1, %2, 0, %1" : "=v"(dt), "+s"(br) : "v"(top));
+  select<L>(r, br, t, d);
+}
+
+// r = (a + b) mod q for a, b in [0, q), q < 2^(32L) (the sum may carry out)
+template <int L>
+__device__ __forceinline__ void mod_add_fw(u32* r, const u32* a, const u32* b, const u32* qv) {
+  u32 s[L], top;
+  u64 cy = add_vv<L>(s, a, b);
+  asm("v_addc_co_u32 %0, %1, 0, 0, %1" : "=v"(top), "+s"(cy));
+  reduce_top<L>(r, s, top, qv);
+}
+
+// r = (a - b) mod q for a, b in [0, q): the difference wraps below zero by
+// exactly 2^(32L), which adding q takes back (no headroom needed)
+template <int L>
+__device__ __forceinline__ void mod_sub_v(u32* r, const u32* a, const u32* b, const u32* qv) {
+  u32 d[L], e[L];
+  u64 br = sub_vv<L>(d, a, b);
+  add_vv<L>(e, d, qv);
+  select<L>(r, br, e, d);
+}
+
+// Canonical butterfly for a full-width modulus: x, y in [0, q), twiddle in
+// digit form; x' = (x + wy) mod q, y' = (x - wy) mod q.
+template <int L>
+__device__ __forceinline__ void ct_butterfly_fw(u32* x, u32* y, const u32* wd, const u32* qd, u32 qinvd,
+                                                const u32* qv) {
+  u32 t[L], tr[L], top;
+  mont_mul_digits<L, true>(t, y, wd, qd, qinvd, &top);
+  reduce_top<L>(tr, t, top, qv);
+  u32 s[L], d[L];
+#pragma unroll
+  for (int j = 0; j < L; j++) s[j] = x[j];
+  mod_add_fw<L>(x, s, tr, qv);
+  mod_sub_v<L>(d, s, tr, qv);
+#pragma unroll
+  for (int j = 0; j < L; j++) y[j] = d[j];
+}
+
+// The same with twiddle 1: (x + y, x - y) mod q.
+template <int L>
+__device__ __forceinline__ void ct_butterfly_one_fw(u32* x, u32* y, const u32* qv) {
+  u32 s[L], d[L];
+#pragma unroll
+  for (int j = 0; j < L; j++) s[j] = x[j];
+  mod_add_fw<L>(x, s, y, qv);
+  mod_sub_v<L>(d, s, y, qv);
+#pragma unroll
+  for (int j = 0; j < L; j++) y[j] = d[j];
+}
+
+// Montgomery product for a full-width modulus, 32-bit limbs (the form of
+// mont_mul_lazy): t = a b 2^(-32L) mod q in [0, q) for a, b in [0, q).  The
+// value (ab + mq) / 2^(32L) < 2q may reach 2^(32L); its carry word is kept and
+// folded into the final trial subtraction.
+template <int L>
+__device__ __forceinline__ void mont_mul_fw(u32* r, const u32* a, const u32* b, const u32* q, u32 qinv,
+                                            const u32* qv) {
+  u32 m[L], t[L];
+  u64 acc = 0;
+  u32 hi;
+#pragma unroll
+  for (int i = 0; i < L; i++) {
+    if (i == 0) {
+      mac_vv_first(acc, hi, a[0], b[0]);
+    } else {
+      mac2_vv_vs_first(acc, hi, a[0], b[i], m[0], q[i]);
+#pragma unroll
+      for (int j = 1; j < i; j++) mac2_vv_vs(acc, hi, a[j], b[i - j], m[j], q[i - j]);
+      mac_vv(acc, hi, a[i], b[0]);
+    }
+    m[i] = (u32)acc * qinv;
+    mac_vs(acc, hi, m[i], q[0]);
+    acc = (acc >> 32) | ((u64)hi << 32);
+  }
+  u32 top = 0;
+#pragma unroll
+  for (int i = L; i < 2 * L; i++) {
+    if (i - L + 1 < L) {
+      mac2_vv_vs_first(acc, hi, a[i - L + 1], b[L - 1], m[i - L + 1], q[L - 1]);
+#pragma unroll
+      for (int j = i - L + 2; j < L; j++) mac2_vv_vs(acc, hi, a[j], b[i - j], m[j], q[i - j]);
+      t[i - L] = (u32)acc;
+      acc = (acc >> 32) | ((u64)hi << 32);
+    } else {
+      t[i - L] = (u32)acc;  // last column: only the carried words are left
+      top = (u32)(acc >> 32);
+    }
+  }
+  reduce_top<L>(r, t, top, qv);
 }
 
 // Copy uniform words into VGPRs once, opaquely, so carry chains that need the

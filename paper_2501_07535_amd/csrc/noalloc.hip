@@ -1,8 +1,8 @@
 // noalloc.hip - the cyclic product for callers that cannot allocate device
 // memory (code under graph capture, tight serving loops, harnesses that forbid
 // hipMalloc).  It runs the same kernels as moma_ntt_cyclic_mul; only the
-// buffers of the two spectra (and, for a full-width modulus, the staging
-// copy) come from a fixed library-wide device array instead of the plan.
+// buffers of the two spectra come from a fixed library-wide device array
+// instead of the plan.
 #include <hip/hip_runtime.h>
 
 #include <mutex>

@@ -44,33 +44,34 @@ bool ntt_batch_variant(int L, uint32_t radix_log, uint32_t threads, NttPassArgs*
   return batch_variant(L, radix_log, threads, a);
 }
 
-int launch_ntt_batch(int L, uint32_t radix_log, bool mul, bool variant, uint32_t threads, size_t lds, uint32_t grid,
-                     const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
-                     hipStream_t s) {
+int launch_ntt_batch(int L, uint32_t radix_log, bool mul, bool variant, bool fw, uint32_t threads, size_t lds,
+                     uint32_t grid, const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items,
+                     uint32_t nitems, hipStream_t s) {
   switch (L) {
-#define CASE(LL)                                                                                                  \
-  case LL:                                                                                                        \
-    return launch_batch_L<LL>(radix_log, mul, variant, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+#define CASE(LL)                                                                                                 \
+  case LL:                                                                                                       \
+    return launch_batch_L<LL>(radix_log, mul, variant, fw, threads, lds, grid, d_passes, d_consts, d_items,      \
+                              nitems, s);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }
   return (int)hipErrorInvalidValue;
 }
 
-void ntt_batch_prepare(int L, uint32_t radix_log, size_t lds) {
+void ntt_batch_prepare(int L, uint32_t radix_log, bool fw, size_t lds) {
   if (lds <= 65536) return;
   switch (L) {
 #define CASE(LL) \
-  case LL: batch_attr_L<LL>(radix_log); return;
+  case LL: batch_attr_L<LL>(radix_log, fw); return;
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }
 }
 
-size_t ntt_consts_bytes(int L) {
+size_t ntt_consts_bytes(int L, bool fw) {
   switch (L) {
 #define CASE(LL) \
-  case LL: return sizeof(NttC<LL>);
+  case LL: return fw ? sizeof(NttC<LL, true>) : sizeof(NttC<LL>);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }
@@ -79,11 +80,16 @@ size_t ntt_consts_bytes(int L) {
 
 void ntt_fill_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc, void* dst) {
   switch (f.L) {
-#define CASE(LL)                                  \
-  case LL: {                                      \
-    NttC<LL> c = make_consts<LL>(f, dc, nc);      \
-    memcpy(dst, &c, sizeof(c));                   \
-    return;                                       \
+#define CASE(LL)                                          \
+  case LL: {                                              \
+    if (f.fw) {                                           \
+      NttC<LL, true> c = make_consts<LL, true>(f, dc, nc); \
+      memcpy(dst, &c, sizeof(c));                         \
+    } else {                                              \
+      NttC<LL> c = make_consts<LL>(f, dc, nc);            \
+      memcpy(dst, &c, sizeof(c));                         \
+    }                                                     \
+    return;                                               \
   }
     MOMA_FOR_EACH_L(CASE)
 #undef CASE

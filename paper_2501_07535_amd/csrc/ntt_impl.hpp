@@ -38,14 +38,15 @@
 
 namespace moma {
 
-template <int L>
+// FW: a full-width modulus (no headroom): canonical values, digits over 32L bits
+template <int L, bool FW = false>
 struct NttC {
   u32 q[L];
-  u32 q2[L];                    // 2q
+  u32 q2[L];                        // 2q (unused for a full-width modulus)
   u32 qinv;
-  u32 nscaled[Digits<L>::D];    // last-pass scale of the inverse, digit Montgomery form
-  u32 qd[Digits<L>::D];         // q in b-bit digits (twiddle multiply)
-  u32 qinvd;                    // -q^-1 mod 2^b
+  u32 nscaled[Digits<L, FW>::D];    // last-pass scale of the inverse, digit Montgomery form
+  u32 qd[Digits<L, FW>::D];         // q in b-bit digits (twiddle multiply)
+  u32 qinvd;                        // -q^-1 mod 2^b
 };
 
 __device__ __forceinline__ u32 rev_bits(u32 x, u32 b) { return b ? (__brev(x) >> (32 - b)) : 0u; }
@@ -76,12 +77,12 @@ __device__ __forceinline__ void load_entry(u32* r, const u32* __restrict__ p) {
   }
 }
 
-// one twiddle entry: digit_stride(L) words, 8-byte aligned
-template <int L>
+// one twiddle entry: digit_stride(L, FW) words, 8-byte aligned
+template <int L, bool FW = false>
 __device__ __forceinline__ void load_digits(u32* r, const u32* __restrict__ p) {
   const uint2* v = reinterpret_cast<const uint2*>(p);
 #pragma unroll
-  for (int i = 0; i < digit_stride(L) / 2; i++) {
+  for (int i = 0; i < digit_stride(L, FW) / 2; i++) {
     uint2 t = v[i];
     r[2 * i] = t.x;
     r[2 * i + 1] = t.y;
@@ -110,8 +111,17 @@ __device__ __forceinline__ u64 tw_pos(const TileGeo& t, u32 sg, u32 lb, u32 g) {
 // addresses (the rows of one column are consecutive across lanes, so every
 // store instruction covers 64-byte runs) instead of back to LDS, so the pass
 // has no separate store phase and the stores drain while other units compute.
-template <int L>
-__device__ __forceinline__ void finish_elem(u32* x, const NttPassArgs& a, const NttC<L>& c) {
+template <int L, bool FW = false>
+__device__ __forceinline__ void finish_elem(u32* x, const NttPassArgs& a, const NttC<L, FW>& c) {
+  if constexpr (FW) {
+    // values are canonical throughout; only the inverse's scale remains
+    if (a.last && a.scale) {
+      u32 y[L], top;
+      mont_mul_digits<L, true>(y, x, c.nscaled, c.qd, c.qinvd, &top);
+      reduce_top<L>(x, y, top, c.q);
+    }
+    return;
+  }
   if (a.last) {
     u32 y[L];
     if (a.scale) {
@@ -126,16 +136,16 @@ __device__ __forceinline__ void finish_elem(u32* x, const NttPassArgs& a, const 
 // LOADG: the pass's first round reads its elements straight from the input in
 // HBM (the addresses the load phase would have filled the LDS rows from)
 // instead of from LDS, so the pass has no separate load phase.
-template <int L, int R, bool FIRST, bool STORE, bool LOADG = false>
+template <int L, int R, bool FIRST, bool STORE, bool LOADG = false, bool FW = false>
 __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
-                                          const NttC<L>& c) {
+                                          const NttC<L, FW>& c) {
   const u32* __restrict__ tw = a.tw;
   const u32 k = t.k;
   const u32 B = 1u << (k - sg0);        // block size (rows) at stage sg0
   const u32 sub = B >> R;                // row spacing of a unit's elements
   const u32 units = (t.E >> R);
-  u32 q2v[L];
-  to_vgprs<L>(q2v, c.q2);
+  u32 q2v[L];  // 2q (lazy butterflies), or q (full width)
+  to_vgprs<L>(q2v, FW ? c.q : c.q2);
   for (u32 b = threadIdx.x; b < units; b += blockDim.x) {
     u32 g = b & (t.C - 1), v = b >> t.logc;
     u32 lb = v >> (k - sg0 - R);
@@ -164,12 +174,18 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
         // p with a zero bit inserted at position kb: the pair (e, e + half) of this stage
         const int e = ((p >> kb) << (kb + 1)) | (p & (half - 1));
         if (FIRST && (e >> (R - s)) == 0) {
-          ct_butterfly_one<L>(x[e], x[e + half], q2v);
+          if constexpr (FW)
+            ct_butterfly_one_fw<L>(x[e], x[e + half], q2v);
+          else
+            ct_butterfly_one<L>(x[e], x[e + half], q2v);
         } else {
           u32 lbk = (lb << s) + (u32)(e >> (R - s));
-          u32 w[digit_stride(L)];
-          load_digits<L>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L));
-          ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
+          u32 w[digit_stride(L, FW)];
+          load_digits<L, FW>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L, FW));
+          if constexpr (FW)
+            ct_butterfly_fw<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
+          else
+            ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
         }
       }
     }
@@ -178,7 +194,7 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
 #pragma unroll
       for (int e = 0; e < (1 << R); e++) {
         const u64 dst = base + ((u64)rev_bits(p0 + e * sub, k) << t.K);
-        finish_elem<L>(x[e], a, c);
+        finish_elem<L, FW>(x[e], a, c);
 #pragma unroll
         for (int j = 0; j < L; j++) a.out[(u64)j * t.n + dst] = x[e][j];
       }
@@ -290,41 +306,50 @@ __device__ __forceinline__ void ntt_round_last(u32* lds, const TileGeo& t, u32 s
 // LDS holds the tile limb-planar: word (j * 2^k + u) * C + g is limb j of row u
 // of group g, so lanes with consecutive g touch consecutive banks.
 // the fused store keeps a unit's finished elements live while it stores them;
-// above 10 limbs that pushes the kernels into scratch memory
-template <int L>
-constexpr bool kFuseStore = L <= 10;
+// above 10 limbs that pushes the kernels into scratch memory (above 9 for a
+// full-width modulus, whose digit multiply at 10 limbs takes one digit more)
+template <int L, bool FW = false>
+constexpr bool kFuseStore = L <= (FW ? 9 : 10);
 
-template <int L, int R>
+template <int L, int R, bool FW = false>
 __device__ __forceinline__ void round_at(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
-                                         const NttC<L>& c, bool store) {
-  if constexpr (kFuseStore<L>) {
+                                         const NttC<L, FW>& c, bool store) {
+  if constexpr (kFuseStore<L, FW>) {
     if (store) {
-      ntt_round<L, R, false, true>(lds, t, sg0, a, c);
+      ntt_round<L, R, false, true, false, FW>(lds, t, sg0, a, c);
       return;
     }
   }
   if (t.K == 0 && sg0 == 0)
-    ntt_round<L, R, true, false>(lds, t, sg0, a, c);
+    ntt_round<L, R, true, false, false, FW>(lds, t, sg0, a, c);
   else
-    ntt_round<L, R, false, false>(lds, t, sg0, a, c);
+    ntt_round<L, R, false, false, false, FW>(lds, t, sg0, a, c);
 }
 
 // Fused pointwise product of a cyclic product's first inverse pass:
 // r = x * y * 2^(-bD) mod q in [0, 2q) for x, y < q (the digit-form multiply
 // with y converted to digits; the last pass's scale constant carries 2^(bD)).
-template <int L>
-__device__ __forceinline__ void pointwise_digits(u32* r, const u32* x, const u32* y, const NttC<L>& c) {
-  u32 yd[Digits<L>::D];
-  to_digits<L>(yd, y);
-  mont_mul_digits<L>(r, x, yd, c.qd, c.qinvd);
+template <int L, bool FW = false>
+__device__ __forceinline__ void pointwise_digits(u32* r, const u32* x, const u32* y, const NttC<L, FW>& c) {
+  u32 yd[Digits<L, FW>::D];
+  to_digits<L, FW>(yd, y);
+  if constexpr (FW) {
+    // canonical result for a full-width modulus
+    u32 t[L], top;
+    mont_mul_digits<L, true>(t, x, yd, c.qd, c.qinvd, &top);
+    reduce_top<L>(r, t, top, c.q);
+  } else {
+    mont_mul_digits<L>(r, x, yd, c.qd, c.qinvd);
+  }
 }
 
 // MUL: the pass also multiplies its input by a.in2 element by element as it
 // loads (first pass of the inverse transform inside a cyclic product).
 // LASTX: the pass ends with ntt_round_last (radix-4 units only; the launcher
 // sets it when fused_last_applies holds, so other launches run unchanged code).
-template <int L, int R, bool MUL, bool LASTX = false>
-__device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const NttC<L>& c, u64 tile) {
+template <int L, int R, bool MUL, bool LASTX = false, bool FW = false>
+__device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const NttC<L, FW>& c, u64 tile) {
+  static_assert(!(FW && LASTX), "the full-width kernels have no cross-lane variant");
   TileGeo t;
   t.k = a.k;
   t.logc = a.logc;
@@ -378,7 +403,7 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
         }
         u32 r[4][L];
 #pragma unroll
-        for (int q4 = 0; q4 < 4; q4++) pointwise_digits<L>(r[q4], x[q4], y[q4], c);
+        for (int q4 = 0; q4 < 4; q4++) pointwise_digits<L, FW>(r[q4], x[q4], y[q4], c);
 #pragma unroll
         for (int j = 0; j < L; j++)
           *reinterpret_cast<uint4*>(lds + (j * t.rows + u) * t.C + g) = make_uint4(r[0][j], r[1][j], r[2][j], r[3][j]);
@@ -400,7 +425,7 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
             x[j] = lds[(j * t.rows + u) * t.C + g + q4];
             y[j] = a.in2[(u64)j * n + src + q4];
           }
-          pointwise_digits<L>(r, x, y, c);
+          pointwise_digits<L, FW>(r, x, y, c);
 #pragma unroll
           for (int j = 0; j < L; j++) lds[(j * t.rows + u) * t.C + g + q4] = r[j];
         }
@@ -431,7 +456,7 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
           x[j] = a.in[(u64)j * n + src];
           y[j] = a.in2[(u64)j * n + src];
         }
-        pointwise_digits<L>(r, x, y, c);
+        pointwise_digits<L, FW>(r, x, y, c);
 #pragma unroll
         for (int j = 0; j < L; j++) lds[(j * t.rows + u) * t.C + g] = r[j];
       } else {
@@ -444,7 +469,7 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
 
   // ---- stages, R at a time in registers
   // later passes with 16+ columns store from the last round's registers
-  const bool fuse = kFuseStore<L> && t.K > 0 && t.C >= 16;
+  const bool fuse = kFuseStore<L, FW> && t.K > 0 && t.C >= 16;
   u32 sg = 0;
   while (sg < t.k) {
     u32 rem = t.k - sg;
@@ -477,13 +502,13 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
     const u32 rr = rem < (u32)R ? rem : (u32)R;
     const bool store = fuse && sg + rr == t.k;
     if (rr == 4) {
-      round_at<L, (R >= 4 ? 4 : 1)>(lds, t, sg, a, c, store);
+      round_at<L, (R >= 4 ? 4 : 1), FW>(lds, t, sg, a, c, store);
     } else if (rr == 3) {
-      round_at<L, (R >= 3 ? 3 : 1)>(lds, t, sg, a, c, store);
+      round_at<L, (R >= 3 ? 3 : 1), FW>(lds, t, sg, a, c, store);
     } else if (rr == 2) {
-      round_at<L, (R >= 2 ? 2 : 1)>(lds, t, sg, a, c, store);
+      round_at<L, (R >= 2 ? 2 : 1), FW>(lds, t, sg, a, c, store);
     } else {
-      round_at<L, 1>(lds, t, sg, a, c, store);
+      round_at<L, 1, FW>(lds, t, sg, a, c, store);
     }
     sg += rr;
     if (!store) __syncthreads();
@@ -492,8 +517,9 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
 
   // ---- store (canonical residues on the last pass), 4 words per lane per limb
   const u32 logn = a.logn;
-  auto finish = [&](u32* x) { finish_elem<L>(x, a, c); };
-  constexpr bool kVecStore = L <= 10;  // 4 elements of L limbs (and the scale multiply) stay in registers
+  auto finish = [&](u32* x) { finish_elem<L, FW>(x, a, c); };
+  // 4 elements of L limbs (and the scale multiply) stay in registers
+  constexpr bool kVecStore = L <= (FW ? 9 : 10);
   if (kVecStore && t.K > 0 && vec_g) {
     // same addresses as the load: 4 consecutive groups of one row
     for (u32 e4 = tid; e4 < (t.E >> 2); e4 += T) {
@@ -568,10 +594,10 @@ struct PassTraits {
 };
 
 // One pass of one transform: workgroup b runs tile b.
-template <int L, int R, bool MUL, bool LASTX>
-__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a, NttC<L> c) {
+template <int L, int R, bool MUL, bool LASTX, bool FW = false>
+__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a, NttC<L, FW> c) {
   extern __shared__ u32 lds[];
-  pass_tile<L, R, MUL, LASTX>(lds, a, c, blockIdx.x);
+  pass_tile<L, R, MUL, LASTX, FW>(lds, a, c, blockIdx.x);
 }
 
 // Whether a pass with radix-4 units ends with ntt_round_last: its stage count
@@ -592,25 +618,26 @@ inline bool fused_last_applies(const NttPassArgs& a, uint32_t threads, uint32_t 
 // its own transform (buffers, size, stages, twiddles) and its modulus constants.
 // Workgroup i runs item i; items are sorted by decreasing cost, so the
 // dispatcher hands out the largest tiles first.
-template <int L, int R, bool MUL, bool LASTX>
+template <int L, int R, bool MUL, bool LASTX, bool FW = false>
 __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_kernel(
-    const NttPassArgs* __restrict__ passes, const NttC<L>* __restrict__ consts, const uint2* __restrict__ items,
+    const NttPassArgs* __restrict__ passes, const NttC<L, FW>* __restrict__ consts, const uint2* __restrict__ items,
     u32 nitems) {
   extern __shared__ u32 lds[];
   const u32 i = blockIdx.x;
   if (i >= nitems) return;
   const uint2 it = items[i];
   const NttPassArgs a = passes[it.x];
-  const NttC<L> c = consts[it.x];
-  pass_tile<L, R, MUL, LASTX>(lds, a, c, it.y);
+  const NttC<L, FW> c = consts[it.x];
+  pass_tile<L, R, MUL, LASTX, FW>(lds, a, c, it.y);
 }
 
 // Twiddle table: entry e = 2^s + i' holds w^(i' * 2^(logn-s-1)) * 2^(32L) mod q.
 // ladder[b] = w^(2^b) * 2^(32L) mod q; the product of the ladder entries for the
 // set bits of the exponent stays in Montgomery form.
-template <int L>
+// FW (full-width modulus): the products keep the carry out of the top limb.
+template <int L, bool FW = false>
 __global__ __launch_bounds__(256) void twiddle_kernel(u32* __restrict__ tw, u64 n, u32 logn,
-                                                      const u32* __restrict__ ladder, NttC<L> c,
+                                                      const u32* __restrict__ ladder, NttC<L, FW> c,
                                                       const u32* __restrict__ one_m, const u32* __restrict__ adj) {
   u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
@@ -626,50 +653,57 @@ __global__ __launch_bounds__(256) void twiddle_kernel(u32* __restrict__ tw, u64 
         u32 w[L], t[L];
 #pragma unroll
         for (int j = 0; j < L; j++) w[j] = ladder[bit * L + j];
-        mont_mul<L>(t, acc, w, c.q, c.qinv);
+        if constexpr (FW)
+          mont_mul_fw<L>(t, acc, w, c.q, c.qinv, c.q);
+        else
+          mont_mul<L>(t, acc, w, c.q, c.qinv);
 #pragma unroll
         for (int j = 0; j < L; j++) acc[j] = t[j];
       }
     }
   }
   // acc = w^x * 2^(32L); times 2^(bD) * 2^(-32L) gives the digit-form Montgomery value
-  u32 ad[L], wm[L], d[digit_stride(L)];
+  constexpr int S = digit_stride(L, FW);
+  u32 ad[L], wm[L], d[S];
 #pragma unroll
   for (int j = 0; j < L; j++) ad[j] = adj[j];
-  mont_mul<L>(wm, acc, ad, c.q, c.qinv);
-  to_digits<L>(d, wm);
-  if (digit_stride(L) > Digits<L>::D) d[digit_stride(L) - 1] = 0;
+  if constexpr (FW)
+    mont_mul_fw<L>(wm, acc, ad, c.q, c.qinv, c.q);
+  else
+    mont_mul<L>(wm, acc, ad, c.q, c.qinv);
+  to_digits<L, FW>(d, wm);
+  if (S > Digits<L, FW>::D) d[S - 1] = 0;
 #pragma unroll
-  for (int j = 0; j < digit_stride(L); j++) tw[e * digit_stride(L) + j] = d[j];
+  for (int j = 0; j < S; j++) tw[e * S + j] = d[j];
 }
 
-template <int L>
-inline NttC<L> make_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc) {
-  NttC<L> c;
-  for (int j = 0; j < Digits<L>::D; j++) c.qd[j] = dc.qd[j];
+template <int L, bool FW = false>
+inline NttC<L, FW> make_consts(const FieldRaw& f, const DigitConsts& dc, const NttConsts* nc) {
+  NttC<L, FW> c;
+  for (int j = 0; j < Digits<L, FW>::D; j++) c.qd[j] = dc.qd[j];
   c.qinvd = dc.qinvd;
   u64 carry = 0;
   for (int j = 0; j < L; j++) {
     c.q[j] = f.q[j];
-    u64 d = ((u64)f.q[j] << 1) + carry;  // 2q limb by limb (q < 2^(32L-4): no overflow)
+    u64 d = ((u64)f.q[j] << 1) + carry;  // 2q limb by limb (wraps for a full-width q, where it is unused)
     c.q2[j] = (u32)d;
     carry = d >> 32;
   }
-  for (int j = 0; j < Digits<L>::D; j++) c.nscaled[j] = nc ? nc->nscale_d[j] : 0;
+  for (int j = 0; j < Digits<L, FW>::D; j++) c.nscaled[j] = nc ? nc->nscale_d[j] : 0;
   c.qinv = f.qinv;
   return c;
 }
 
-template <int L, int R, bool MUL, bool LASTX>
-int launch_pass_LRM(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
+template <int L, int R, bool MUL, bool LASTX, bool FW = false>
+int launch_pass_LRM(const NttC<L, FW>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
   size_t lds = (size_t)L * ((size_t)1 << (a.k + a.logc)) * sizeof(u32);
   static std::atomic<bool> attr_set{false};  // several host threads may launch at once
   if (lds > 65536 && !attr_set.load(std::memory_order_acquire)) {
-    (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R, MUL, LASTX>,
+    (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R, MUL, LASTX, FW>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set.store(true, std::memory_order_release);
   }
-  hipLaunchKernelGGL((ntt_pass_kernel<L, R, MUL, LASTX>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
+  hipLaunchKernelGGL((ntt_pass_kernel<L, R, MUL, LASTX, FW>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
   return (int)hipGetLastError();
 }
 
@@ -719,9 +753,26 @@ int launch_pass_LR(const NttC<L>& c, const NttPassArgs& a, uint32_t threads, uin
                : launch_pass_LRX<L, R, false>(c, a, threads, tiles, s);
 }
 
+// full-width modulus: radix-2 and radix-4 units, no cross-lane variant
+template <int L>
+int launch_pass_fw(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& nc,
+                   uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s) {
+  NttC<L, true> c = make_consts<L, true>(f, dc, &nc);
+  if (radix_log == 1)
+    return a.in2 ? launch_pass_LRM<L, 1, true, false, true>(c, a, threads, tiles, s)
+                 : launch_pass_LRM<L, 1, false, false, true>(c, a, threads, tiles, s);
+  if constexpr (L <= kMaxLimbsRadix4Fw) {
+    if (radix_log == 2)
+      return a.in2 ? launch_pass_LRM<L, 2, true, false, true>(c, a, threads, tiles, s)
+                   : launch_pass_LRM<L, 2, false, false, true>(c, a, threads, tiles, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
 template <int L>
 int launch_pass_L(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& nc,
                   uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s) {
+  if (f.fw) return launch_pass_fw<L>(f, dc, a, nc, threads, tiles, radix_log, s);
   NttC<L> c = make_consts<L>(f, dc, &nc);
   // register blocking is limited by the VGPR budget: 2^r elements of L limbs
   if (radix_log == 1) return launch_pass_LR<L, 1>(c, a, threads, tiles, s);
@@ -737,15 +788,15 @@ int launch_pass_L(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a
   return (int)hipErrorInvalidValue;
 }
 
-template <int L, int R, bool LASTX>
+template <int L, int R, bool LASTX, bool FW = false>
 int launch_batch_LRX(bool mul, uint32_t threads, size_t lds, uint32_t grid, const NttPassArgs* d_passes,
                      const void* d_consts, const uint2* d_items, uint32_t nitems, hipStream_t s) {
   if (mul)
-    hipLaunchKernelGGL((ntt_batch_kernel<L, R, true, LASTX>), dim3(grid), dim3(threads), lds, s, d_passes,
-                       (const NttC<L>*)d_consts, d_items, nitems);
+    hipLaunchKernelGGL((ntt_batch_kernel<L, R, true, LASTX, FW>), dim3(grid), dim3(threads), lds, s, d_passes,
+                       (const NttC<L, FW>*)d_consts, d_items, nitems);
   else
-    hipLaunchKernelGGL((ntt_batch_kernel<L, R, false, LASTX>), dim3(grid), dim3(threads), lds, s, d_passes,
-                       (const NttC<L>*)d_consts, d_items, nitems);
+    hipLaunchKernelGGL((ntt_batch_kernel<L, R, false, LASTX, FW>), dim3(grid), dim3(threads), lds, s, d_passes,
+                       (const NttC<L, FW>*)d_consts, d_items, nitems);
   return (int)hipGetLastError();
 }
 
@@ -761,9 +812,20 @@ int launch_batch_LR(bool mul, bool lastx, uint32_t threads, size_t lds, uint32_t
 }
 
 template <int L>
-int launch_batch_L(uint32_t radix_log, bool mul, bool lastx, uint32_t threads, size_t lds, uint32_t grid,
+int launch_batch_L(uint32_t radix_log, bool mul, bool lastx, bool fw, uint32_t threads, size_t lds, uint32_t grid,
                    const NttPassArgs* d_passes, const void* d_consts, const uint2* d_items, uint32_t nitems,
                    hipStream_t s) {
+  if (fw) {
+    // full-width modulus: radix-2 and radix-4 units, no cross-lane variant
+    if (lastx) return (int)hipErrorInvalidValue;
+    if (radix_log == 1)
+      return launch_batch_LRX<L, 1, false, true>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+    if constexpr (L <= kMaxLimbsRadix4Fw) {
+      if (radix_log == 2)
+        return launch_batch_LRX<L, 2, false, true>(mul, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
+    }
+    return (int)hipErrorInvalidValue;
+  }
   if (radix_log == 1)
     return launch_batch_LR<L, 1>(mul, lastx, threads, lds, grid, d_passes, d_consts, d_items, nitems, s);
   if constexpr (L <= kMaxLimbsRadix4) {
@@ -798,7 +860,18 @@ void batch_attr_LR() {
 }
 
 template <int L>
-void batch_attr_L(uint32_t radix_log) {
+void batch_attr_L(uint32_t radix_log, bool fw) {
+  if (fw) {
+    const void* k[4] = {(const void*)ntt_batch_kernel<L, 1, false, false, true>,
+                        (const void*)ntt_batch_kernel<L, 1, true, false, true>, nullptr, nullptr};
+    if constexpr (L <= kMaxLimbsRadix4Fw) {
+      k[2] = (const void*)ntt_batch_kernel<L, 2, false, false, true>;
+      k[3] = (const void*)ntt_batch_kernel<L, 2, true, false, true>;
+    }
+    for (const void* f : k)
+      if (f) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return;
+  }
   if (radix_log == 1) batch_attr_LR<L, 1>();
   if constexpr (L <= kMaxLimbsRadix4) {
     if (radix_log == 2) batch_attr_LR<L, 2>();
@@ -814,13 +887,19 @@ void batch_attr_L(uint32_t radix_log) {
 template <int L>
 int launch_tw_L(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t n, uint32_t logn,
                        const uint32_t* d_ladder, hipStream_t s) {
-  NttC<L> c = make_consts<L>(f, dc, nullptr);
   // the ladder buffer carries one_m and then adj after the logn ladder entries
   const u32* one_m = d_ladder + (size_t)logn * L;
   const u32* adj = one_m + L;
   u64 blocks = (n + 255) / 256;
-  hipLaunchKernelGGL((twiddle_kernel<L>), dim3((unsigned)blocks), dim3(256), 0, s, tw, n, logn, d_ladder, c, one_m,
-                     adj);
+  if (f.fw) {
+    NttC<L, true> c = make_consts<L, true>(f, dc, nullptr);
+    hipLaunchKernelGGL((twiddle_kernel<L, true>), dim3((unsigned)blocks), dim3(256), 0, s, tw, n, logn, d_ladder, c,
+                       one_m, adj);
+  } else {
+    NttC<L> c = make_consts<L>(f, dc, nullptr);
+    hipLaunchKernelGGL((twiddle_kernel<L>), dim3((unsigned)blocks), dim3(256), 0, s, tw, n, logn, d_ladder, c,
+                       one_m, adj);
+  }
   return (int)hipGetLastError();
 }
 
@@ -828,9 +907,9 @@ int launch_tw_L(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t
 #define MOMA_NTT_DECLARE(PREFIX, LL)                                                                              \
   PREFIX template int launch_pass_L<LL>(const FieldRaw&, const DigitConsts&, const NttPassArgs&, const NttConsts&, \
                                         uint32_t, uint64_t, uint32_t, hipStream_t);                                 \
-  PREFIX template int launch_batch_L<LL>(uint32_t, bool, bool, uint32_t, size_t, uint32_t, const NttPassArgs*,     \
-                                         const void*, const uint2*, uint32_t, hipStream_t);                         \
-  PREFIX template void batch_attr_L<LL>(uint32_t);                                                                  \
+  PREFIX template int launch_batch_L<LL>(uint32_t, bool, bool, bool, uint32_t, size_t, uint32_t,                  \
+                                         const NttPassArgs*, const void*, const uint2*, uint32_t, hipStream_t);     \
+  PREFIX template void batch_attr_L<LL>(uint32_t, bool);                                                            \
   PREFIX template int launch_tw_L<LL>(const FieldRaw&, const DigitConsts&, uint32_t*, uint64_t, uint32_t,          \
                                       const uint32_t*, hipStream_t);
 #define MOMA_NTT_INSTANTIATE(LL) MOMA_NTT_DECLARE(, LL)

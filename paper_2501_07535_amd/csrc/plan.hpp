@@ -38,7 +38,6 @@ struct NttPlan {
   NttConsts mul_consts;           // inverse after a fused pointwise product
   uint32_t* scratch = nullptr;    // for in-place multi-pass calls
   uint32_t* spectra = nullptr;    // 2 x n x L words: the two forward transforms of a cyclic product
-  uint32_t* stage = nullptr;      // n x L words: full-width moduli run through it (storage has L - 1 planes)
   NttSchedule sched;
   std::vector<NttPass> passes;
   std::mutex mu;  // guards scratch allocation and schedule changes
@@ -49,7 +48,6 @@ struct NttPlan {
     (void)hipFree(inv.ladder);
     (void)hipFree(scratch);
     (void)hipFree(spectra);
-    (void)hipFree(stage);
   }
 };
 
@@ -59,13 +57,14 @@ extern thread_local std::string g_detail;
 int hip_fail(int e, const char* what);
 int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* out);
 int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, std::shared_ptr<NttPlan>* out);
-uint32_t max_radix_log(int L);
-int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out);
+// fw: a full-width modulus, whose kernels have radix-2 units, and radix-4 up to 9 limbs
+uint32_t max_radix_log(int L, bool fw = false);
+int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out, bool fw = false);
 NttSchedule default_schedule(int L, uint32_t logn);
 NttSchedule batch_schedule(int L, uint32_t logn);
 int run_plan(NttPlan& p, bool inverse, const uint32_t* d_in, uint32_t* d_out, hipStream_t s);
 // ext: NULL, or caller-provided device scratch of cyclic_mul_scratch_words(p)
-// words used in place of the plan's spectra (and staging) buffers, so the call
+// words used in place of the plan's spectra buffer, so the call
 // allocates nothing
 int run_cyclic_mul(NttPlan& p, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, hipStream_t s,
                    uint32_t* ext = nullptr);
@@ -83,8 +82,8 @@ struct BlasJobRec {
 };
 size_t blas_consts_bytes(int L);
 void blas_fill_consts(const FieldRaw& f, const BlasArgs& a, void* dst);
-int launch_blas_batch(int op, int L, uint32_t variant, const void* recs, const void* consts, const uint2* items,
-                      uint32_t nitems, hipStream_t s);
+int launch_blas_batch(int op, int L, uint32_t variant, bool fw, const void* recs, const void* consts,
+                      const uint2* items, uint32_t nitems, hipStream_t s);
 // vmul's product variant for a compute limb count (capi.cpp)
 uint32_t vmul_variant(int L);
 // alpha (storage limbs words) in Montgomery form for axpy, validated < q
@@ -105,7 +104,7 @@ int count_noncanonical(const FieldRaw& f, const uint32_t* d_x, uint64_t n, hipSt
 int check_inputs(const FieldRaw& f, const uint32_t* const* d_x, int nx, uint64_t n, hipStream_t s,
                  uint32_t* d_part = nullptr);
 // tuner (tune.cpp)
-std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn);
+std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn, bool fw = false);
 bool tune_db_best(const std::string& dev, int L, uint32_t logn, NttSchedule* out);
 std::string current_device_name();
 // cost model (costmodel.cpp): predicted log-time per schedule; MOMA_E_UNSUPPORTED without a model
@@ -115,6 +114,6 @@ int costmodel_scores(int L, uint32_t logn, const std::vector<NttSchedule>& cands
 bool costmodel_pick(int L, uint32_t logn, NttSchedule* out);
 // a new plan's schedule: the timing database's best, else the cost model's
 // pick, else the fixed rule of default_schedule
-NttSchedule initial_schedule(int L, uint32_t logn);
+NttSchedule initial_schedule(int L, uint32_t logn, bool fw = false);
 
 }  // namespace moma

@@ -50,18 +50,18 @@ static std::string device_name() {
 }
 
 // every shape the pass kernels can run, in a fixed order
-std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn) {
+std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn, bool fw) {
   std::vector<NttSchedule> out;
   std::string keep = g_detail;
   for (uint32_t tl = 5; tl <= 14; tl++) {
     bool single = logn <= tl;
     for (uint32_t cl : {2u, 3u, 4u, 5u}) {
       if (single && cl != 2) continue;  // the column count does not apply to one-pass plans
-      for (uint32_t r = 1; r <= max_radix_log(L); r++) {
+      for (uint32_t r = 1; r <= max_radix_log(L, fw); r++) {
         for (uint32_t t : {64u, 128u, 256u, 512u, 1024u}) {
           NttSchedule s{single ? logn : tl, single ? 0u : cl, t, r};
           std::vector<NttPass> ps;
-          if (plan_passes(L, logn, s, &ps) != MOMA_OK) continue;
+          if (plan_passes(L, logn, s, &ps, fw) != MOMA_OK) continue;
           // more threads than units per round would idle whole waves
           uint32_t e = single ? logn : tl;
           uint32_t units = 1u << (e > r ? e - r : 0);
@@ -107,7 +107,7 @@ std::string current_device_name() { return device_name(); }
 static int time_schedule(NttPlan& p, const NttSchedule& s, const uint32_t* din, uint32_t* dout, uint32_t warmup,
                          uint32_t reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float* us) {
   std::vector<NttPass> ps;
-  int rc = plan_passes(p.fe->f.L, p.logn, s, &ps);
+  int rc = plan_passes(p.fe->f.L, p.logn, s, &ps, p.fe->f.fw);
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(p.mu);
@@ -151,7 +151,8 @@ static int tune(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t l
   if (o) opts = *o;
   if (opts.reps == 0) opts.reps = 1;
   int L = p->fe->f.L;
-  std::vector<NttSchedule> cands = enumerate_schedules(L, p->logn);
+  const bool fw = p->fe->f.fw != 0;
+  std::vector<NttSchedule> cands = enumerate_schedules(L, p->logn, fw);
   uint32_t feasible = (uint32_t)cands.size();
   if (opts.top_k > 0) {
     std::vector<float> sc;
@@ -214,7 +215,7 @@ static int tune(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t l
   (void)hipFree(dout);
   NttSchedule chosen = (rc == MOMA_OK && best >= 0) ? cands[best] : prev;
   std::vector<NttPass> ps;
-  (void)plan_passes(L, p->logn, chosen, &ps);
+  (void)plan_passes(L, p->logn, chosen, &ps, fw);
   {
     std::lock_guard<std::mutex> lk(p->mu);
     p->sched = chosen;
@@ -222,8 +223,10 @@ static int tune(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t l
   }
   if (rc) return rc;
   {
+    // the database's rows are keyed by compute limbs and describe the
+    // headroom kernels; a full-width plan's timings stay out of it
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_rows.insert(g_rows.end(), rows.begin(), rows.end());
+    if (!fw) g_rows.insert(g_rows.end(), rows.begin(), rows.end());
   }
   if (res) {
     res->best = {chosen.tile_log, chosen.col_log, chosen.threads, chosen.radix_log};

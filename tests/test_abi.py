@@ -72,11 +72,8 @@ def test_blas_rejects_bad_modulus(case):
         rc = lib.moma_vmul(_w(q + 1, L), L, 10, DUMMY, DUMMY, DUMMY, None)
         assert rc == moma.MOMA_E_MODULUS
     elif case == "q_too_wide":
-        # a full-width 1024-bit modulus needs 33 internal limbs
-        wide = (1 << 1023) + 1
-        rc = lib.moma_vsub(_w(wide, 32), 32, 10, DUMMY, DUMMY, DUMMY, None)
-        assert rc == moma.MOMA_E_UNSUPPORTED
-        # full width below 1024 bits is accepted (n = 0: validation only)
+        # full width (no headroom) is accepted up to 1024 bits (n = 0: validation only)
+        assert lib.moma_vsub(_w((1 << 1023) + 1, 32), 32, 0, None, None, None, None) == 0
         assert lib.moma_vsub(_w((1 << 255) + 1, L), L, 0, None, None, None, None) == 0
     elif case == "q_null":
         rc = lib.moma_vadd(None, L, 10, DUMMY, DUMMY, DUMMY, None)

@@ -81,8 +81,8 @@ def test_noalloc_matches_cyclic_mul_on_two_calls(lam, big, small):
 
 
 def test_noalloc_full_width_and_in_place():
-    """A full-width modulus (staged through the same array) with the output
-    over one input, against the plain call on copies of the inputs."""
+    """A full-width modulus with the output over one input, against the plain
+    call."""
     import torch
 
     import paper_2501_07535_amd as moma
