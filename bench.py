@@ -105,7 +105,8 @@ def parse():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="time the default schedule without autotuning")
     ap.add_argument("--schedule", default=None,
-                    help="tile_log,col_log,threads,radix_log: use this launch shape instead of autotuning")
+                    help="tile_log,col_log,threads,radix_log[,mul_variant]: use this launch shape instead of "
+                         "autotuning")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line, print one JSON line per size of the transform sweep "
                          "(2^16..2^24 at 256 bits, 2^20 at 128/384/1024 bits, and 2^20 with full-width "
@@ -117,6 +118,9 @@ def parse():
                     help="instead of the headline line, print one JSON line per modular BLAS op and width "
                          "(vadd/vsub/vmul/axpy at n=2^24, 256/384/768 bits)")
     ap.add_argument("--blas-logn", type=int, default=24)
+    ap.add_argument("--mulalg", action="store_true",
+                    help="instead of the headline line, compare the butterfly's schoolbook and Karatsuba word "
+                         "products (Eq. (mulk)) at n=2^12 for 128, 256, 384 and 768 bits")
     ap.add_argument("--peaks", action="store_true",
                     help="instead of the headline line, print the measured issue rates and HBM bandwidths that "
                          "price the roofline")
@@ -234,6 +238,61 @@ def blas(args):
         torch.cuda.empty_cache()
 
 
+def mulalg(args):
+    """The butterfly's word-product form (Eq. (mulk)) at n = 2^12: for each width
+    the autotuner times every launch shape with the schoolbook and (radix-2
+    shapes) the Karatsuba digit product; the best of each form is re-timed,
+    then both forms on the best Karatsuba shape, with outputs checked against
+    the oracle's transform."""
+    import torch
+
+    import oracle
+    import paper_2501_07535_amd as moma
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    logn = 12
+    n = 1 << logn
+    for lam in (128, 256, 384, 768):
+        f = mi.find_prime(lam, 0)
+        L, q = f.limbs, f.q
+        w = f.root(n)
+        x = mi.residues(f, n, L, 2, logn)
+        want = oracle.ntt_radix2(q, L, w, x)
+        dx = torch.from_numpy(mi.to_planar(x).view(np.int32)).to(dev)
+        dy = torch.empty_like(dx)
+        moma.tune_db_clear()
+        moma.ntt_tune(q, w, n, L, reps=3, warmup=1)
+        rows = moma.tune_db_rows()
+
+        def best(pred):
+            r = min((r for r in rows if pred(r["sched"])), key=lambda r: r["us"])
+            return tuple(r["sched"])
+        picks = {"schoolbook_best": best(lambda s: s[4] == 0), "schoolbook_radix2_best": best(
+            lambda s: s[4] == 0 and s[3] == 1), "karatsuba_best": best(lambda s: s[4] == 1)}
+        picks["schoolbook_on_karatsuba_shape"] = picks["karatsuba_best"][:4] + (0,)
+        res, ok = {}, True
+        for name, sch in picks.items():
+            moma.ntt_set_schedule(q, w, n, L, sch)
+            us = _time_fwd(moma, torch, stream, dx, dy, q, w, 5, 200)
+            ok &= bool((mi.from_planar(dy.cpu().numpy().view(np.uint32)) == want).all())
+            res[name] = {"schedule": list(sch), "us": round(us, 3)}
+        D = -(-(32 * L - 2) // (29 if L <= 28 else 28))
+        h, g = (D + 1) // 2, D // 2
+        print(json.dumps({"lambda": lam, "limbs": L, "digits": D, "log2_n": logn,
+                          "digit_products_per_multiply": {"schoolbook": 2 * D * D,
+                                                          "karatsuba": 2 * h * h + g * g + D * D},
+                          **res,
+                          "karatsuba_over_schoolbook_best": round(res["karatsuba_best"]["us"] /
+                                                                  res["schoolbook_best"]["us"], 3),
+                          "karatsuba_over_schoolbook_same_shape": round(
+                              res["karatsuba_best"]["us"] / res["schoolbook_on_karatsuba_shape"]["us"], 3),
+                          "outputs_vs_oracle": ok}), flush=True)
+        moma.ntt_set_schedule(q, w, n, L, None)
+        del dx, dy
+        moma.shutdown()
+    moma.tune_db_clear()
+
+
 def peaks():
     """The library's issue-rate and bandwidth probes, as rates and as fractions
     of the vendor peaks (39.32 T full-rate lane operations/s, 8 TB/s)."""
@@ -267,6 +326,9 @@ def main():
     if args.peaks:
         peaks()
         return
+    if args.mulalg:
+        mulalg(args)
+        return
     import torch
 
     import paper_2501_07535_amd as moma
@@ -286,7 +348,7 @@ def main():
     default_us = None if args.forward_only else _time_fwd(moma, torch, stream, dx, dy, q, w, 3, 20)
     tuned = None
     if args.schedule:
-        moma.ntt_set_schedule(q, w, n, L, tuple(int(v) for v in args.schedule.split(",")))
+        moma.ntt_set_schedule(q, w, n, L, tuple(int(v) for v in args.schedule.split(",")))  # 4 or 5 fields
     elif not args.no_tune:
         # the library's autotuner picks the launch shape before the timed region
         tuned = moma.ntt_tune(q, w, n, L, reps=3, warmup=1)

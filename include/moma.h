@@ -233,14 +233,21 @@ int moma_ntt_describe(const uint32_t* q, const uint32_t* omega, uint64_t n, uint
  *   threads   - threads per workgroup, a multiple of 64 in [64, 1024];
  *   radix_log - stages each thread runs in registers per LDS round trip
  *               (radix 2, 4, 8 or 16; radix 16 up to 2 limbs, radix 8 up to 5,
- *               radix 4 up to 10).
+ *               radix 4 up to 10; a full-width modulus: radix 4 up to 9);
+ *   mul_variant - how the butterfly's twiddle multiply forms its word
+ *               products (Eq. (mulk)): MOMA_NTT_MUL_SCHOOLBOOK, or
+ *               MOMA_NTT_MUL_KARATSUBA (one level of Karatsuba on the
+ *               multiply's digits; radix 2 only, 2 to 24 compute limbs, not
+ *               for full-width moduli; batches run the schoolbook form).
  * Every schedule computes the same result; only speed differs.
  */
+enum moma_ntt_mul_variant { MOMA_NTT_MUL_SCHOOLBOOK = 0, MOMA_NTT_MUL_KARATSUBA = 1 };
 typedef struct moma_ntt_schedule {
   uint32_t tile_log;
   uint32_t col_log;
   uint32_t threads;
   uint32_t radix_log;
+  uint32_t mul_variant;
 } moma_ntt_schedule_t;
 
 /* Set the schedule of the plan for (q, omega, n, limbs); NULL restores the
@@ -288,15 +295,18 @@ typedef struct moma_tune_result {
 
 int moma_ntt_tune(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, const moma_tune_opts_t* opts,
                   moma_tune_result_t* result);
-/* The feasible shapes for a compute limb count and size, in the tuner's order.
- * Writes at most `max` entries to out (may be NULL) and the total to *count. */
+/* The feasible shapes for a compute limb count and size, in the tuner's order
+ * (the schoolbook shapes, then the radix-2 ones again with the Karatsuba
+ * multiply where it applies).  Writes at most `max` entries to out (may be
+ * NULL) and the total to *count. */
 int moma_ntt_candidates(uint32_t limbs_compute, uint32_t log2_n, moma_ntt_schedule_t* out, uint32_t max,
                         uint32_t* count);
 
 /* Timing database: one row per timed shape.  Plans created after a load start
  * from the fastest recorded shape for their (compute limbs, log2 n) on the
  * same device name.  CSV: device,limbs,log2_n,tile_log,col_log,threads,
- * radix_log,us,reps. */
+ * radix_log,us,reps,mul_variant (rows without the last column load as
+ * schoolbook).  Tuning a full-width plan records nothing. */
 typedef struct moma_tune_row {
   uint32_t limbs;           /* compute limbs */
   uint32_t log2_n;
@@ -311,10 +321,10 @@ int moma_tune_db_save(const char* path);
 int moma_tune_db_load(const char* path);
 
 /*
- * Learned cost model: an FP32 perceptron 6 -> 64 -> 64 -> 1 (ReLU) predicting
- * log(microseconds) of a schedule from six features (moma_costmodel_features:
+ * Learned cost model: an FP32 perceptron 7 -> 64 -> 64 -> 1 (ReLU) predicting
+ * log(microseconds) of a schedule from seven features (moma_costmodel_features:
  * log2 n, compute limbs, log2 radix, stages fused per pass, log2 threads,
- * log2 LDS bytes), trained on the GPU by the library's own kernels with Adam
+ * log2 LDS bytes, Karatsuba multiply 0/1), trained on the GPU by the library's own kernels with Adam
  * on mean squared error.  Features and targets are z-scored with the training
  * set's statistics, which are saved with the weights.  While a model is
  * loaded (or trained), new plans whose shape the timing database does not
@@ -328,22 +338,23 @@ typedef struct moma_train_opts {
   uint64_t seed;            /* initial weights and minibatch order (SplitMix64) */
 } moma_train_opts_t;
 
-int moma_costmodel_features(uint32_t limbs_compute, uint32_t log2_n, const moma_ntt_schedule_t* sched, float* out6);
-/* Train from host arrays features[rows][6] and targets log_us[rows]; replaces the
+#define MOMA_COSTMODEL_FEATURES 7
+int moma_costmodel_features(uint32_t limbs_compute, uint32_t log2_n, const moma_ntt_schedule_t* sched, float* out7);
+/* Train from host arrays features[rows][7] and targets log_us[rows]; replaces the
  * current model.  *final_mse (may be NULL) is the training-set mean squared
  * error in (log us)^2. */
 int moma_costmodel_train(const float* features, const float* log_us, uint32_t rows, const moma_train_opts_t* opts,
                          float* final_mse);
-/* Predict log(us) for host features[rows][6]. */
+/* Predict log(us) for host features[rows][7]. */
 int moma_costmodel_predict(const float* features, uint32_t rows, float* log_us);
 int moma_costmodel_save(const char* path);
 int moma_costmodel_load(const char* path);
 void moma_costmodel_clear(void);
 
 /* The network's kernels on raw device arrays (features already normalised),
- * for checking them against a reference: parameters are W1[64][6], b1[64],
+ * for checking them against a reference: parameters are W1[64][7], b1[64],
  * W2[64][64], b2[64], W3[64], b3 (moma_mlp_nparams() floats).
- *   forward: y[r] for rows x[r][6];
+ *   forward: y[r] for rows x[r][7];
  *   grad:    gradient of mean((y - t)^2) into grad[nparams] and the loss into
  *            *d_loss; allocates a workspace and synchronises `stream`;
  *   adam:    one bias-corrected Adam step (step >= 1) on params, m, v. */

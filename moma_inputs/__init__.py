@@ -399,13 +399,13 @@ def batch_inputs(jobs: list[BatchJob], config: int = 3) -> list[np.ndarray]:
 
 # ----------------------------------------------------------------------------- cost-model inputs
 
-MLP_IN, MLP_H = 6, 64
+MLP_IN, MLP_H = 7, 64
 MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
 
 
 def mlp_init(seed: int) -> np.ndarray:
     """He-normal initial weights (N(0, 2/fan_in)), zero biases, flat float64 in the
-    layout W1[64][6], b1, W2[64][64], b2, W3[64], b3.  Normal draws come from
+    layout W1[64][7], b1, W2[64][64], b2, W3[64], b3.  Normal draws come from
     SplitMix64 by the Box-Muller transform: u = (top 53 bits + 1) / 2^53,
     z = sqrt(-2 ln u1) cos(2 pi u2)."""
     sizes = [(MLP_H * MLP_IN, MLP_IN), (MLP_H, 0), (MLP_H * MLP_H, MLP_H), (MLP_H, 0), (MLP_H, MLP_H), (1, 0)]

@@ -238,7 +238,7 @@ def cyclic_conv(q: int, L: int, a, b) -> np.ndarray:
 
 # ----------------------------------------------------------------- MLP (FP64)
 
-MLP_IN, MLP_H = 6, 64
+MLP_IN, MLP_H = 7, 64
 
 
 def mlp_nparams() -> int:
@@ -251,7 +251,7 @@ def _d(a):
 
 
 def mlp_forward(params, x) -> np.ndarray:
-    """Network output for each row of x (rows x 6)."""
+    """Network output for each row of x (rows x MLP_IN)."""
     p, pp = _d(params)
     xx, xp = _d(x)
     y = np.zeros(xx.shape[0])

@@ -475,13 +475,15 @@ int oracle_cyclic_conv(const limb_t *q, int L, int64_t n, const limb_t *a, const
 
 /* ================================================================== MLP
  * FP64 reference for the learned schedule cost model: a multilayer perceptron
- * 6 -> 64 -> 64 -> 1 with ReLU after the two hidden layers, mean squared error
- * loss, and Adam (Kingma and Ba, ICLR 2015) with bias correction.
+ * 7 -> 64 -> 64 -> 1 with ReLU after the two hidden layers, mean squared error
+ * loss, and Adam (Kingma and Ba, ICLR 2015) with bias correction.  The seven
+ * inputs are the schedule features (the six launch-shape features and the
+ * butterfly's word-product form, schoolbook or Karatsuba, Eq. (mulk)).
  * Parameters are one flat array:
- *   W1[64][6], b1[64], W2[64][64], b2[64], W3[64], b3   (4673 values)
+ *   W1[64][7], b1[64], W2[64][64], b2[64], W3[64], b3   (4737 values)
  * with W[o][i] the weight from input i to output o.
  */
-#define MLP_IN 6
+#define MLP_IN 7
 #define MLP_H 64
 #define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1)
 

@@ -77,12 +77,18 @@ for _name in ("moma_pack_planar", "moma_unpack_planar"):
 
 
 class Schedule(ctypes.Structure):
-    """Launch shape of a transform plan (see moma_ntt_schedule_t)."""
+    """Launch shape of a transform plan (see moma_ntt_schedule_t): as a tuple
+    (tile_log, col_log, threads, radix_log, mul_variant); a 4-tuple means the
+    schoolbook multiply (mul_variant 0)."""
     _fields_ = [("tile_log", ctypes.c_uint32), ("col_log", ctypes.c_uint32), ("threads", ctypes.c_uint32),
-                ("radix_log", ctypes.c_uint32)]
+                ("radix_log", ctypes.c_uint32), ("mul_variant", ctypes.c_uint32)]
 
     def as_tuple(self):
-        return (self.tile_log, self.col_log, self.threads, self.radix_log)
+        return (self.tile_log, self.col_log, self.threads, self.radix_log, self.mul_variant)
+
+
+NTT_MUL_SCHOOLBOOK, NTT_MUL_KARATSUBA = 0, 1
+COSTMODEL_FEATURES = 7
 
 
 _lib.moma_ntt_set_schedule.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Schedule)]
@@ -404,7 +410,8 @@ def ntt_describe(q: int, omega: int, n: int, limbs: int) -> dict:
 
 
 def ntt_set_schedule(q: int, omega: int, n: int, limbs: int, sched=None):
-    """Set the plan's launch shape: a (tile_log, col_log, threads, radix_log) tuple, or None for the default."""
+    """Set the plan's launch shape: a (tile_log, col_log, threads, radix_log[, mul_variant]) tuple, or None
+    for the plan's initial choice."""
     ptr = None
     if sched is not None:
         ptr = ctypes.byref(Schedule(*[int(v) for v in sched]))
@@ -532,7 +539,7 @@ def tune_db_load(path: str):
 # ----------------------------------------------------------------- cost model
 
 def costmodel_features(limbs_compute: int, log2_n: int, sched) -> list:
-    out = (ctypes.c_float * 6)()
+    out = (ctypes.c_float * COSTMODEL_FEATURES)()
     _check(_lib.moma_costmodel_features(limbs_compute, log2_n, ctypes.byref(Schedule(*sched)), out))
     return list(out)
 
@@ -544,7 +551,7 @@ def _f32(a):
 
 
 def costmodel_train(features, log_us, epochs: int = 200, batch: int = 256, lr: float = 3e-3, seed: int = 1) -> float:
-    """Train the model on the GPU from features (rows, 6) and log-microsecond targets; returns the final MSE."""
+    """Train the model on the GPU from features (rows, 7) and log-microsecond targets; returns the final MSE."""
     f, fp = _f32(features)
     t, tp = _f32(log_us)
     mse = ctypes.c_float(0)

@@ -11,6 +11,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import time
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,24 +28,29 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["ntt_inst_e.hip", "ntt_inst_d.hip", "ntt_inst_c.hip", "ntt_inst_b.hip", "ntt_inst_a.hip", "ntt.hip", "blas.hip", "mlp.hip", "probe.hip", "noalloc.hip",
+SOURCES = ["ntt_inst_d.hip", "ntt_inst_f.hip", "ntt_inst_e.hip", "ntt_inst_g.hip", "ntt_inst_c.hip", "ntt_inst_b.hip",
+           "ntt_inst_a.hip", "ntt.hip", "blas.hip", "mlp.hip", "probe.hip", "noalloc.hip",
            "capi.cpp", "batch.cpp", "tune.cpp", "costmodel.cpp"]
 
 
-def _compile(src: str) -> str:
+def _compile(src: str) -> tuple[str, float]:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "not a recognized feature" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{msg}")
-    return obj
+    return obj, time.time() - t0
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        done = list(ex.map(_compile, SOURCES))
+    objs = [o for o, _ in done]
+    if verbose:
+        print("compile seconds:", ", ".join(f"{s} {t:.0f}" for s, (_, t) in zip(SOURCES, done)))
     tmp = LIB + ".tmp"
     subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs])
     os.replace(tmp, LIB)

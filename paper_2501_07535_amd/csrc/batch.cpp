@@ -210,6 +210,8 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       passes = p->passes;
       sched = p->sched;
     }
+    // the batch kernels run the schoolbook butterfly
+    sched.kara = 0;
     // A plan's own schedule is chosen for a lone call, where small transforms
     // want small tiles to spread over the chip.  In a batch the other jobs
     // fill the chip, so jobs up to 2^18 points take large tiles (fewer passes

@@ -131,6 +131,10 @@ int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>
     return set_error(MOMA_E_ARG, "threads must be a multiple of 64 in [64, 1024]");
   if (s.radix_log < 1 || s.radix_log > max_radix_log(L, fw))
     return set_error(MOMA_E_UNSUPPORTED, "radix_log out of range for this limb count");
+  if (s.kara > 1) return set_error(MOMA_E_ARG, "unknown multiply variant");
+  if (s.kara && (fw || s.radix_log != 1 || L < 2 || L > kMaxLimbsKara))
+    return set_error(MOMA_E_UNSUPPORTED,
+                     "the Karatsuba butterfly runs radix-2 units at 2 to 24 compute limbs (not full width)");
   if (s.threads > ntt_max_threads(L, s.radix_log))
     return set_error(MOMA_E_UNSUPPORTED, "too many threads for this limb count and radix");
   if (s.tile_log < 1 || s.tile_log > 20) return set_error(MOMA_E_ARG, "tile_log out of range");
@@ -406,7 +410,7 @@ static int enqueue_passes(NttPlan& p, const std::vector<NttPass>& passes, const 
     a.logc = ps.logc;
     a.last = (i + 1 == P) ? 1u : 0u;
     a.scale = (scale && i + 1 == P) ? 1u : 0u;
-    int e = launch_ntt_pass(f, p.fe->dc, a, c, sched.threads, ps.tiles, sched.radix_log, s);
+    int e = launch_ntt_pass(f, p.fe->dc, a, c, sched.threads, ps.tiles, sched.radix_log, sched.kara, s);
     if (e) return hip_fail(e, "ntt pass launch");
   }
   return MOMA_OK;
@@ -833,7 +837,8 @@ int moma_ntt_set_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, 
   std::shared_ptr<NttPlan> p;
   int rc = get_plan(q, omega, n, limbs, &p);
   if (rc) return rc;
-  NttSchedule s = sched ? NttSchedule{sched->tile_log, sched->col_log, sched->threads, sched->radix_log}
+  NttSchedule s = sched ? NttSchedule{sched->tile_log, sched->col_log, sched->threads, sched->radix_log,
+                                      sched->mul_variant}
                         : initial_schedule(p->fe->f.L, p->logn, p->fe->f.fw);
   std::vector<NttPass> ps;
   rc = plan_passes(p->fe->f.L, p->logn, s, &ps, p->fe->f.fw);
@@ -855,6 +860,7 @@ int moma_ntt_get_schedule(const uint32_t* q, const uint32_t* omega, uint64_t n, 
   sched->col_log = p->sched.col_log;
   sched->threads = p->sched.threads;
   sched->radix_log = p->sched.radix_log;
+  sched->mul_variant = p->sched.kara;
   return MOMA_OK;
 }
 
@@ -863,7 +869,7 @@ int moma_ntt_default_schedule(uint32_t limbs_compute, uint32_t log2_n, moma_ntt_
   if (limbs_compute < 1 || limbs_compute > (uint32_t)kMaxLimbs || log2_n < 1 || log2_n > MOMA_MAX_LOG_N)
     return set_error(MOMA_E_ARG, "limbs or log2_n out of range");
   NttSchedule s = default_schedule((int)limbs_compute, log2_n);
-  *sched = {s.tile_log, s.col_log, s.threads, s.radix_log};
+  *sched = {s.tile_log, s.col_log, s.threads, s.radix_log, s.kara};
   return MOMA_OK;
 }
 

@@ -25,6 +25,10 @@ constexpr int digit_stride(int L, bool fw = false) {  // table words per entry
 constexpr int kMaxLimbsRadix4 = 10;
 constexpr int kMaxLimbsRadix8 = 5;
 constexpr int kMaxLimbsRadix16 = 2;
+// the Karatsuba form of the butterfly's multiply (Eq. (mulk)): radix-2 units,
+// 2 to 24 limbs (up to 768 bits, the widths its comparison with schoolbook
+// covers; its 2D - 1 live column sums cost registers the wider units lack)
+constexpr int kMaxLimbsKara = 24;
 // full-width moduli: radix-4 units up to 9 limbs (at 10 the digit multiply
 // takes one digit more and the unit no longer fits the register budget)
 constexpr int kMaxLimbsRadix4Fw = 9;
@@ -75,11 +79,18 @@ struct NttPassArgs {
 };
 
 // Launch shape of a transform: LDS tile of 2^tile_log elements, 2^col_log
-// groups per tile in multi-pass plans, threads per workgroup, and stages per
-// register unit (radix 2^radix_log).
+// groups per tile in multi-pass plans, threads per workgroup, stages per
+// register unit (radix 2^radix_log), and the butterfly's word-product form
+// (kara: one level of Karatsuba, Eq. (mulk); 0: schoolbook).
 struct NttSchedule {
   uint32_t tile_log, col_log, threads, radix_log;
+  uint32_t kara = 0;
 };
+
+// arithmetic of a transform kernel: lazy butterflies with the schoolbook or
+// the Karatsuba digit product, or canonical ones for a full-width modulus
+enum NttArith { kArithLazy = 0, kArithFull = 1, kArithKara = 2 };
+
 
 struct NttConsts {
   // last-pass scale of the inverse transform, as D b-bit digits: n^{-1} 2^(bD)
@@ -101,7 +112,7 @@ int set_error(int code, const std::string& detail);
 int launch_blas(int op, const FieldRaw& f, const BlasArgs& a, hipStream_t s);
 int launch_zero_planes(uint32_t* out, uint64_t n, int from_plane, int to_plane, hipStream_t s);
 int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& c,
-                    uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s);
+                    uint32_t threads, uint64_t tiles, uint32_t radix_log, uint32_t kara, hipStream_t s);
 // batched transforms: one launch runs items (pass record, tile) of many plans
 // (fw: full-width moduli, whose kernels and constants are of their own kind)
 size_t ntt_consts_bytes(int L, bool fw);

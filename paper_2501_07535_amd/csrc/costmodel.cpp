@@ -38,7 +38,7 @@ size_t mlp_grad_workspace_floats(unsigned rows);
 int launch_mlp_adam(float* p, const float* g, float* m, float* v, unsigned step, float lr, float b1, float b2,
                     float eps, hipStream_t s);
 
-static const int kFeat = 6;
+static const int kFeat = MOMA_COSTMODEL_FEATURES;
 
 struct CostModel {
   bool ready = false;
@@ -76,6 +76,7 @@ void schedule_features(int L, uint32_t logn, const NttSchedule& s, float* f) {
   f[3] = (float)fused;
   f[4] = (float)std::log2((double)s.threads);
   f[5] = (float)std::log2(lds);
+  f[6] = (float)s.kara;
 }
 
 static int predict_locked(const float* feats, uint32_t rows, float* out) {
@@ -152,7 +153,7 @@ static void he_init(uint64_t seed, std::vector<float>* p) {
     double u2 = ((double)(sm64(key, ctr++) >> 11) + 1.0) / 9007199254740992.0;
     return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
   };
-  const int H = 64, I = 6;
+  const int H = 64, I = kFeat;
   int o = 0;
   for (int i = 0; i < H * I; i++) (*p)[o + i] = (float)(normal() * std::sqrt(2.0 / I));
   o += H * I + H;
@@ -275,10 +276,10 @@ int moma_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, 
   return e ? hip_fail(e, "mlp adam") : MOMA_OK;
 }
 
-int moma_costmodel_features(uint32_t limbs_compute, uint32_t log2_n, const moma_ntt_schedule_t* sched, float* out6) {
-  if (!sched || !out6) return set_error(MOMA_E_ARG, "NULL pointer");
-  NttSchedule s{sched->tile_log, sched->col_log, sched->threads, sched->radix_log};
-  schedule_features((int)limbs_compute, log2_n, s, out6);
+int moma_costmodel_features(uint32_t limbs_compute, uint32_t log2_n, const moma_ntt_schedule_t* sched, float* out7) {
+  if (!sched || !out7) return set_error(MOMA_E_ARG, "NULL pointer");
+  NttSchedule s{sched->tile_log, sched->col_log, sched->threads, sched->radix_log, sched->mul_variant};
+  schedule_features((int)limbs_compute, log2_n, s, out7);
   return MOMA_OK;
 }
 

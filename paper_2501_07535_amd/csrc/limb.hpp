@@ -269,21 +269,6 @@ __device__ __forceinline__ void from_digits(u32* y, const u32* d) {
   }
 }
 
-// Bit 32L (and above) of the value of digits d, whose last digit may exceed
-// b bits: the carry word of a full-width result below 2q < 2^(32L+1).
-template <int L>
-__device__ __forceinline__ u32 top_of_digits(const u32* d) {
-  constexpr int b = Digits<L, true>::b, D = Digits<L, true>::D;
-  constexpr int i = (32 * L) / b, s = (32 * L) % b;
-  if constexpr (i >= D) {
-    return d[D - 1] >> (32 * L - b * (D - 1));  // above the last digit's b bits
-  } else {
-    u32 v = d[i] >> s;
-    if constexpr (i + 1 < D) v |= d[i + 1] << (b - s);
-    return v;
-  }
-}
-
 // t = y * w * 2^(-bD) mod q in [0, 2q), w given as digits (Montgomery form for
 // R = 2^(bD)), y < 4q in 32-bit limbs (y < q for a full-width modulus, FW).
 // Product scanning: column i sums every digit product y_j w_{i-j} and
@@ -295,7 +280,8 @@ __device__ __forceinline__ void mont_mul_digits(u32* t, const u32* y, const u32*
                                                 u32* top = nullptr) {
   constexpr int b = Digits<L, FW>::b, D = Digits<L, FW>::D;
   constexpr u32 mask = Digits<L, FW>::mask;
-  u32 a[D], m[D], r[D];
+  static_assert(b * D >= 32 * L - (FW ? 0 : 2), "the digits cover the result limbs");
+  u32 a[D], m[D];
   to_digits<L, FW>(a, y);
   u64 acc = 0;
 #pragma unroll
@@ -308,16 +294,109 @@ __device__ __forceinline__ void mont_mul_digits(u32* t, const u32* y, const u32*
     acc += (u64)m[i] * qd[0];
     acc >>= b;
   }
+  // the upper columns give the result digits; each result limb leaves as soon
+  // as its 32 bits are known (digit positions are compile-time constants), so
+  // the digits are never all live at once
+  u64 bits = 0;
+  int nb = 0, j = 0;
+#pragma unroll
+  for (int i = D; i < 2 * D; i++) {
+    u32 dig;
+    if (i < 2 * D - 1) {
+#pragma unroll
+      for (int jj = i - D + 1; jj < D; jj++) acc += (u64)a[jj] * wd[i - jj] + (u64)m[jj] * qd[i - jj];
+      dig = (u32)acc & mask;
+      acc >>= b;
+    } else {
+      dig = (u32)acc;  // the last digit carries everything above
+    }
+    bits |= (u64)dig << nb;
+    nb += b;
+    while (nb >= 32 && j < L) {
+      t[j++] = (u32)bits;
+      bits >>= 32;
+      nb -= 32;
+    }
+  }
+  // bD is at least 32L - 2 (at least 32L for a full-width modulus), so at most
+  // the top limb is still in the buffer here: its bits above bD come from the
+  // last digit, which is wider than b
+  if (j < L) t[j] = (u32)bits;
+  if constexpr (FW) *top = (u32)bits;  // bit 32L of a full-width result below 2q
+}
+
+// The same product with its first half (the digit product y w) by one level
+// of Karatsuba (Eq. (mulk)) on the digits: with y = y1 B^h + y0 and
+// w = w1 B^h + w0 (B = 2^b, h = ceil(D/2)), y w = z2 B^(2h) + z1 B^h + z0 where
+// z1 = (y0 + y1)(w0 + w1) - z0 - z2.  The digit sums have b + 1 bits and need
+// no carry; every product column is gathered as an exact 64-bit sum (it
+// equals the schoolbook column, below D 2^(2b)), so the Montgomery
+// reduction that follows is unchanged.  Word products: 2h^2 + (D - h)^2
+// instead of D^2, for 2D - 1 extra column additions and 2h - 1 column
+// subtractions.
+template <int L>
+__device__ __forceinline__ void mont_mul_digits_kara(u32* t, const u32* y, const u32* wd, const u32* qd, u32 qinvd) {
+  constexpr int b = Digits<L>::b, D = Digits<L>::D, h = (D + 1) / 2, g = D - h;
+  constexpr u32 mask = Digits<L>::mask;
+  u32 a[D], m[D], r[D], sa[h], sw[h];
+  to_digits<L>(a, y);
+#pragma unroll
+  for (int i = 0; i < h; i++) {
+    sa[i] = a[i] + (i < g ? a[h + i] : 0u);
+    sw[i] = wd[i] + (i < g ? wd[h + i] : 0u);
+  }
+  u64 p[2 * D - 1];
+#pragma unroll
+  for (int c = 0; c < 2 * D - 1; c++) p[c] = 0;
+#pragma unroll
+  for (int c = 0; c < 2 * h - 1; c++) {
+    u64 z0 = 0, zm = 0, z2 = 0;
+#pragma unroll
+    for (int i = (c < h ? 0 : c - h + 1); i <= (c < h ? c : h - 1); i++) {
+      z0 += (u64)a[i] * wd[c - i];
+      zm += (u64)sa[i] * sw[c - i];
+    }
+    if (c <= 2 * g - 2) {
+#pragma unroll
+      for (int i = (c < g ? 0 : c - g + 1); i <= (c < g ? c : g - 1); i++) z2 += (u64)a[h + i] * wd[h + c - i];
+      p[c + 2 * h] += z2;
+    }
+    p[c] += z0;
+    p[c + h] += zm - z0 - z2;  // the cross terms: exact, non-negative
+  }
+  u64 acc = 0;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    acc += p[i];
+#pragma unroll
+    for (int j = 0; j < i; j++) acc += (u64)m[j] * qd[i - j];
+    m[i] = ((u32)acc * qinvd) & mask;
+    acc += (u64)m[i] * qd[0];
+    acc >>= b;
+  }
 #pragma unroll
   for (int i = D; i < 2 * D - 1; i++) {
+    acc += p[i];
 #pragma unroll
-    for (int j = i - D + 1; j < D; j++) acc += (u64)a[j] * wd[i - j] + (u64)m[j] * qd[i - j];
+    for (int j = i - D + 1; j < D; j++) acc += (u64)m[j] * qd[i - j];
     r[i - D] = (u32)acc & mask;
     acc >>= b;
   }
   r[D - 1] = (u32)acc;
-  from_digits<L, FW>(t, r);
-  if constexpr (FW) *top = top_of_digits<L>(r);
+  from_digits<L>(t, r);
+}
+
+// Lazy butterfly with the Karatsuba form of the twiddle multiply.
+template <int L>
+__device__ __forceinline__ void ct_butterfly_kara(u32* x, u32* y, const u32* wd, const u32* qd, u32 qinvd,
+                                                  const u32* q2v) {
+  u32 xr[L], t[L], d[L], s[L];
+  u64 br = sub_vv<L>(s, x, q2v);  // x - 2q; borrow <=> x < 2q
+  select<L>(xr, br, x, s);
+  mont_mul_digits_kara<L>(t, y, wd, qd, qinvd);
+  add_vv<L>(x, xr, t);
+  sub_vv<L>(d, xr, t);
+  add_vv<L>(y, d, q2v);
 }
 
 // ----------------------------------------------------------------- full width
@@ -491,6 +570,30 @@ __device__ __forceinline__ void ct_butterfly_lazy_v(u32* x, u32* y, const u32* w
   add_vv<L>(x, xr, t);
   sub_vv<L>(d, xr, t);
   add_vv<L>(y, d, q2v);
+}
+
+// The additions of the lazy butterfly once its product t = w*y in [0, 2q) is
+// known: x <- x mod 2q; y = x - t + 2q; x = x + t.
+template <int L>
+__device__ __forceinline__ void ct_lazy_tail(u32* x, u32* y, const u32* t, const u32* q2v) {
+  u32 xr[L], d[L], s[L];
+  u64 br = sub_vv<L>(s, x, q2v);
+  select<L>(xr, br, x, s);
+  add_vv<L>(x, xr, t);
+  sub_vv<L>(d, xr, t);
+  add_vv<L>(y, d, q2v);
+}
+
+// The same for a full-width modulus: t (with its carry word) reduced, then
+// (x + t, x - t) mod q.
+template <int L>
+__device__ __forceinline__ void ct_fw_tail(u32* x, u32* y, const u32* t, u32 top, const u32* qv) {
+  u32 tr[L], s[L];
+  reduce_top<L>(tr, t, top, qv);
+#pragma unroll
+  for (int j = 0; j < L; j++) s[j] = x[j];
+  mod_add_fw<L>(x, s, tr, qv);
+  mod_sub_v<L>(y, s, tr, qv);
 }
 
 // Barrett constants for r = a*b mod q, following Listings 1 and 4 generalised to

@@ -1,17 +1,18 @@
 // mlp.hip - FP32 kernels of the learned schedule cost model: a perceptron
-// 6 -> 64 -> 64 -> 1 with ReLU hidden layers, mean squared error, Adam.
+// 7 -> 64 -> 64 -> 1 with ReLU hidden layers, mean squared error, Adam.
 //
-// Parameters are one flat array: W1[64][6], b1[64], W2[64][64], b2[64], W3[64], b3
+// Parameters are one flat array: W1[64][7], b1[64], W2[64][64], b2[64], W3[64], b3
 // (4673 floats, 18.3 KiB), staged into LDS by every forward/backward workgroup.
 // One thread handles one row (sample) in the forward and per-row backward
 // kernels; weight gradients are reductions over rows, one thread per parameter
 // with a fixed summation order (deterministic).  The network is tiny next to
 // the timings it replaces, so plain FP32 VALU is used throughout.
+#include "../../include/moma.h"
 #include "common.hpp"
 
 namespace moma {
 
-constexpr int kIn = 6, kH = 64;
+constexpr int kIn = MOMA_COSTMODEL_FEATURES, kH = 64;
 constexpr int kOffB1 = kH * kIn, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH, kOffW3 = kOffB2 + kH,
               kOffB3 = kOffW3 + kH, kNParam = kOffB3 + 1;
 

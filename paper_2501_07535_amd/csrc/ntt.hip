@@ -30,10 +30,10 @@ uint32_t ntt_max_threads(int L, uint32_t radix_log) {
 }
 
 int launch_ntt_pass(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& c,
-                    uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s) {
+                    uint32_t threads, uint64_t tiles, uint32_t radix_log, uint32_t kara, hipStream_t s) {
   switch (f.L) {
 #define CASE(LL) \
-  case LL: return launch_pass_L<LL>(f, dc, a, c, threads, tiles, radix_log, s);
+  case LL: return launch_pass_L<LL>(f, dc, a, c, threads, tiles, radix_log, kara, s);
     MOMA_FOR_EACH_L(CASE)
 #undef CASE
   }

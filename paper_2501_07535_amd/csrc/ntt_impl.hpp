@@ -136,14 +136,93 @@ __device__ __forceinline__ void finish_elem(u32* x, const NttPassArgs& a, const 
 // LOADG: the pass's first round reads its elements straight from the input in
 // HBM (the addresses the load phase would have filled the LDS rows from)
 // instead of from LDS, so the pass has no separate load phase.
-template <int L, int R, bool FIRST, bool STORE, bool LOADG = false, bool FW = false>
+// Wide limbs, radix-2 units: registers, not instructions, bound these kernels
+// (one or two waves per SIMD), so a unit reads the bottom element, forms the
+// product w*y, and only then reads the top element and copies 2q (or q) into
+// VGPRs for the additions; neither is live across the multiply.
+constexpr int kLateLoadLimbs = 11;
+
+template <int L, bool FIRST, bool STORE, int AR>
+__device__ __forceinline__ void round_late(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
+                                           const NttC<L, AR == kArithFull>& c) {
+  constexpr bool FW = AR == kArithFull;
+  const u32* __restrict__ tw = a.tw;
+  const u32 k = t.k;
+  const u32 B = 1u << (k - sg0);  // block size (rows) at stage sg0; the pair is B/2 rows apart
+  const u32 units = t.E >> 1;
+  for (u32 b = threadIdx.x; b < units; b += blockDim.x) {
+    u32 g = b & (t.C - 1), v = b >> t.logc;
+    u32 lb = v >> (k - sg0 - 1);
+    u32 p0 = lb * B + (v & ((B >> 1) - 1));
+    const u32 r0 = p0, r1 = p0 + (B >> 1);
+    u32 x[L], y[L];
+    if (FIRST && lb == 0) {
+      // twiddle 1: no multiply
+#pragma unroll
+      for (int j = 0; j < L; j++) {
+        x[j] = lds[(j * t.rows + r0) * t.C + g];
+        y[j] = lds[(j * t.rows + r1) * t.C + g];
+      }
+      u32 qv[L];
+      to_vgprs<L>(qv, FW ? c.q : c.q2);
+      if constexpr (FW)
+        ct_butterfly_one_fw<L>(x, y, qv);
+      else
+        ct_butterfly_one<L>(x, y, qv);
+    } else {
+      u32 w[digit_stride(L, FW)], p[L], top = 0;
+      load_digits<L, FW>(w, tw + tw_pos(t, sg0, lb, g) * digit_stride(L, FW));
+#pragma unroll
+      for (int j = 0; j < L; j++) y[j] = lds[(j * t.rows + r1) * t.C + g];
+      if constexpr (FW)
+        mont_mul_digits<L, true>(p, y, w, c.qd, c.qinvd, &top);
+      else if constexpr (AR == kArithKara)
+        mont_mul_digits_kara<L>(p, y, w, c.qd, c.qinvd);
+      else
+        mont_mul_digits<L>(p, y, w, c.qd, c.qinvd);
+#pragma unroll
+      for (int j = 0; j < L; j++) x[j] = lds[(j * t.rows + r0) * t.C + g];
+      u32 qv[L];
+      to_vgprs<L>(qv, FW ? c.q : c.q2);
+      if constexpr (FW)
+        ct_fw_tail<L>(x, y, p, top, qv);
+      else
+        ct_lazy_tail<L>(x, y, p, qv);
+    }
+    if constexpr (STORE) {
+      const u64 base = (t.ro << (t.K + k)) + t.b0 + g;
+      finish_elem<L, FW>(x, a, c);
+      finish_elem<L, FW>(y, a, c);
+      const u64 d0 = base + ((u64)rev_bits(r0, k) << t.K), d1 = base + ((u64)rev_bits(r1, k) << t.K);
+#pragma unroll
+      for (int j = 0; j < L; j++) {
+        a.out[(u64)j * t.n + d0] = x[j];
+        a.out[(u64)j * t.n + d1] = y[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < L; j++) {
+        lds[(j * t.rows + r0) * t.C + g] = x[j];
+        lds[(j * t.rows + r1) * t.C + g] = y[j];
+      }
+    }
+  }
+}
+
+// AR: the kernel's arithmetic (NttArith)
+template <int L, int R, bool FIRST, bool STORE, bool LOADG = false, int AR = kArithLazy>
 __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
-                                          const NttC<L, FW>& c) {
+                                          const NttC<L, AR == kArithFull>& c) {
+  constexpr bool FW = AR == kArithFull;
   const u32* __restrict__ tw = a.tw;
   const u32 k = t.k;
   const u32 B = 1u << (k - sg0);        // block size (rows) at stage sg0
   const u32 sub = B >> R;                // row spacing of a unit's elements
   const u32 units = (t.E >> R);
+  if constexpr (R == 1 && !LOADG && L >= kLateLoadLimbs) {
+    round_late<L, FIRST, STORE, AR>(lds, t, sg0, a, c);
+    return;
+  }
   u32 q2v[L];  // 2q (lazy butterflies), or q (full width)
   to_vgprs<L>(q2v, FW ? c.q : c.q2);
   for (u32 b = threadIdx.x; b < units; b += blockDim.x) {
@@ -184,6 +263,8 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
           load_digits<L, FW>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L, FW));
           if constexpr (FW)
             ct_butterfly_fw<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
+          else if constexpr (AR == kArithKara)
+            ct_butterfly_kara<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
           else
             ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
         }
@@ -311,19 +392,19 @@ __device__ __forceinline__ void ntt_round_last(u32* lds, const TileGeo& t, u32 s
 template <int L, bool FW = false>
 constexpr bool kFuseStore = L <= (FW ? 9 : 10);
 
-template <int L, int R, bool FW = false>
+template <int L, int R, int AR = kArithLazy>
 __device__ __forceinline__ void round_at(u32* lds, const TileGeo& t, u32 sg0, const NttPassArgs& a,
-                                         const NttC<L, FW>& c, bool store) {
-  if constexpr (kFuseStore<L, FW>) {
+                                         const NttC<L, AR == kArithFull>& c, bool store) {
+  if constexpr (kFuseStore<L, AR == kArithFull>) {
     if (store) {
-      ntt_round<L, R, false, true, false, FW>(lds, t, sg0, a, c);
+      ntt_round<L, R, false, true, false, AR>(lds, t, sg0, a, c);
       return;
     }
   }
   if (t.K == 0 && sg0 == 0)
-    ntt_round<L, R, true, false, false, FW>(lds, t, sg0, a, c);
+    ntt_round<L, R, true, false, false, AR>(lds, t, sg0, a, c);
   else
-    ntt_round<L, R, false, false, false, FW>(lds, t, sg0, a, c);
+    ntt_round<L, R, false, false, false, AR>(lds, t, sg0, a, c);
 }
 
 // Fused pointwise product of a cyclic product's first inverse pass:
@@ -347,9 +428,11 @@ __device__ __forceinline__ void pointwise_digits(u32* r, const u32* x, const u32
 // loads (first pass of the inverse transform inside a cyclic product).
 // LASTX: the pass ends with ntt_round_last (radix-4 units only; the launcher
 // sets it when fused_last_applies holds, so other launches run unchanged code).
-template <int L, int R, bool MUL, bool LASTX = false, bool FW = false>
-__device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const NttC<L, FW>& c, u64 tile) {
-  static_assert(!(FW && LASTX), "the full-width kernels have no cross-lane variant");
+template <int L, int R, bool MUL, bool LASTX = false, int AR = kArithLazy>
+__device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const NttC<L, AR == kArithFull>& c,
+                                          u64 tile) {
+  constexpr bool FW = AR == kArithFull;
+  static_assert(AR == kArithLazy || !LASTX, "only the lazy schoolbook kernels have the cross-lane variant");
   TileGeo t;
   t.k = a.k;
   t.logc = a.logc;
@@ -502,13 +585,13 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
     const u32 rr = rem < (u32)R ? rem : (u32)R;
     const bool store = fuse && sg + rr == t.k;
     if (rr == 4) {
-      round_at<L, (R >= 4 ? 4 : 1), FW>(lds, t, sg, a, c, store);
+      round_at<L, (R >= 4 ? 4 : 1), AR>(lds, t, sg, a, c, store);
     } else if (rr == 3) {
-      round_at<L, (R >= 3 ? 3 : 1), FW>(lds, t, sg, a, c, store);
+      round_at<L, (R >= 3 ? 3 : 1), AR>(lds, t, sg, a, c, store);
     } else if (rr == 2) {
-      round_at<L, (R >= 2 ? 2 : 1), FW>(lds, t, sg, a, c, store);
+      round_at<L, (R >= 2 ? 2 : 1), AR>(lds, t, sg, a, c, store);
     } else {
-      round_at<L, 1, FW>(lds, t, sg, a, c, store);
+      round_at<L, 1, AR>(lds, t, sg, a, c, store);
     }
     sg += rr;
     if (!store) __syncthreads();
@@ -594,10 +677,11 @@ struct PassTraits {
 };
 
 // One pass of one transform: workgroup b runs tile b.
-template <int L, int R, bool MUL, bool LASTX, bool FW = false>
-__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a, NttC<L, FW> c) {
+template <int L, int R, bool MUL, bool LASTX, int AR = kArithLazy>
+__global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_pass_kernel(NttPassArgs a,
+                                                                                 NttC<L, AR == kArithFull> c) {
   extern __shared__ u32 lds[];
-  pass_tile<L, R, MUL, LASTX, FW>(lds, a, c, blockIdx.x);
+  pass_tile<L, R, MUL, LASTX, AR>(lds, a, c, blockIdx.x);
 }
 
 // Whether a pass with radix-4 units ends with ntt_round_last: its stage count
@@ -628,7 +712,7 @@ __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_ker
   const uint2 it = items[i];
   const NttPassArgs a = passes[it.x];
   const NttC<L, FW> c = consts[it.x];
-  pass_tile<L, R, MUL, LASTX, FW>(lds, a, c, it.y);
+  pass_tile<L, R, MUL, LASTX, FW ? kArithFull : kArithLazy>(lds, a, c, it.y);
 }
 
 // Twiddle table: entry e = 2^s + i' holds w^(i' * 2^(logn-s-1)) * 2^(32L) mod q.
@@ -694,16 +778,17 @@ inline NttC<L, FW> make_consts(const FieldRaw& f, const DigitConsts& dc, const N
   return c;
 }
 
-template <int L, int R, bool MUL, bool LASTX, bool FW = false>
-int launch_pass_LRM(const NttC<L, FW>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles, hipStream_t s) {
+template <int L, int R, bool MUL, bool LASTX, int AR = kArithLazy>
+int launch_pass_LRM(const NttC<L, AR == kArithFull>& c, const NttPassArgs& a, uint32_t threads, uint64_t tiles,
+                    hipStream_t s) {
   size_t lds = (size_t)L * ((size_t)1 << (a.k + a.logc)) * sizeof(u32);
   static std::atomic<bool> attr_set{false};  // several host threads may launch at once
   if (lds > 65536 && !attr_set.load(std::memory_order_acquire)) {
-    (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R, MUL, LASTX, FW>,
+    (void)hipFuncSetAttribute((const void*)ntt_pass_kernel<L, R, MUL, LASTX, AR>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set.store(true, std::memory_order_release);
   }
-  hipLaunchKernelGGL((ntt_pass_kernel<L, R, MUL, LASTX, FW>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
+  hipLaunchKernelGGL((ntt_pass_kernel<L, R, MUL, LASTX, AR>), dim3((unsigned)tiles), dim3(threads), lds, s, a, c);
   return (int)hipGetLastError();
 }
 
@@ -759,21 +844,31 @@ int launch_pass_fw(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& 
                    uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s) {
   NttC<L, true> c = make_consts<L, true>(f, dc, &nc);
   if (radix_log == 1)
-    return a.in2 ? launch_pass_LRM<L, 1, true, false, true>(c, a, threads, tiles, s)
-                 : launch_pass_LRM<L, 1, false, false, true>(c, a, threads, tiles, s);
+    return a.in2 ? launch_pass_LRM<L, 1, true, false, kArithFull>(c, a, threads, tiles, s)
+                 : launch_pass_LRM<L, 1, false, false, kArithFull>(c, a, threads, tiles, s);
   if constexpr (L <= kMaxLimbsRadix4Fw) {
     if (radix_log == 2)
-      return a.in2 ? launch_pass_LRM<L, 2, true, false, true>(c, a, threads, tiles, s)
-                   : launch_pass_LRM<L, 2, false, false, true>(c, a, threads, tiles, s);
+      return a.in2 ? launch_pass_LRM<L, 2, true, false, kArithFull>(c, a, threads, tiles, s)
+                   : launch_pass_LRM<L, 2, false, false, kArithFull>(c, a, threads, tiles, s);
   }
   return (int)hipErrorInvalidValue;
 }
 
 template <int L>
 int launch_pass_L(const FieldRaw& f, const DigitConsts& dc, const NttPassArgs& a, const NttConsts& nc,
-                  uint32_t threads, uint64_t tiles, uint32_t radix_log, hipStream_t s) {
-  if (f.fw) return launch_pass_fw<L>(f, dc, a, nc, threads, tiles, radix_log, s);
+                  uint32_t threads, uint64_t tiles, uint32_t radix_log, uint32_t kara, hipStream_t s) {
+  if (f.fw)
+    return kara ? (int)hipErrorInvalidValue : launch_pass_fw<L>(f, dc, a, nc, threads, tiles, radix_log, s);
   NttC<L> c = make_consts<L>(f, dc, &nc);
+  if (kara) {
+    // the Karatsuba butterfly: radix-2 units, 2 to 24 limbs, no cross-lane variant
+    if constexpr (L >= 2 && L <= kMaxLimbsKara) {
+      if (radix_log == 1)
+        return a.in2 ? launch_pass_LRM<L, 1, true, false, kArithKara>(c, a, threads, tiles, s)
+                     : launch_pass_LRM<L, 1, false, false, kArithKara>(c, a, threads, tiles, s);
+    }
+    return (int)hipErrorInvalidValue;
+  }
   // register blocking is limited by the VGPR budget: 2^r elements of L limbs
   if (radix_log == 1) return launch_pass_LR<L, 1>(c, a, threads, tiles, s);
   if constexpr (L <= kMaxLimbsRadix4) {
@@ -906,7 +1001,7 @@ int launch_tw_L(const FieldRaw& f, const DigitConsts& dc, uint32_t* tw, uint64_t
 // the per-limb-count entry points, instantiated once (in ntt_inst_*.hip)
 #define MOMA_NTT_DECLARE(PREFIX, LL)                                                                              \
   PREFIX template int launch_pass_L<LL>(const FieldRaw&, const DigitConsts&, const NttPassArgs&, const NttConsts&, \
-                                        uint32_t, uint64_t, uint32_t, hipStream_t);                                 \
+                                        uint32_t, uint64_t, uint32_t, uint32_t, hipStream_t);                       \
   PREFIX template int launch_batch_L<LL>(uint32_t, bool, bool, bool, uint32_t, size_t, uint32_t,                  \
                                          const NttPassArgs*, const void*, const uint2*, uint32_t, hipStream_t);     \
   PREFIX template void batch_attr_L<LL>(uint32_t, bool);                                                            \

@@ -1,8 +1,8 @@
-// ntt_inst_d.hip - transform kernels for compute limb counts 23..32.
+// ntt_inst_d.hip - transform kernels for compute limb counts 5..6.
 #include "ntt_impl.hpp"
 
 namespace moma {
 
-MOMA_NTT_INSTANTIATE(23) MOMA_NTT_INSTANTIATE(24) MOMA_NTT_INSTANTIATE(25) MOMA_NTT_INSTANTIATE(26) MOMA_NTT_INSTANTIATE(27) MOMA_NTT_INSTANTIATE(28) MOMA_NTT_INSTANTIATE(29) MOMA_NTT_INSTANTIATE(30) MOMA_NTT_INSTANTIATE(31) MOMA_NTT_INSTANTIATE(32)
+MOMA_NTT_INSTANTIATE(5) MOMA_NTT_INSTANTIATE(6)
 
 }  // namespace moma

@@ -33,6 +33,7 @@ struct TuneRow {
   uint32_t L, logn, tile_log, col_log, threads, radix_log;
   float us;
   uint32_t reps;
+  uint32_t kara = 0;  // the butterfly's word products by Karatsuba (Eq. (mulk))
 };
 
 static std::mutex g_tune_mu;
@@ -49,7 +50,9 @@ static std::string device_name() {
   return s + "/" + std::to_string(p.multiProcessorCount) + "cu";
 }
 
-// every shape the pass kernels can run, in a fixed order
+// every shape the pass kernels can run, in a fixed order: the schoolbook
+// butterflies first, then the radix-2 shapes again with the Karatsuba form of
+// the twiddle multiply (2 to 24 limbs; not for full-width moduli)
 std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn, bool fw) {
   std::vector<NttSchedule> out;
   std::string keep = g_detail;
@@ -80,6 +83,15 @@ std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn, bool fw) {
       }
     }
   }
+  if (!fw && L >= 2 && L <= kMaxLimbsKara) {
+    const size_t nschool = out.size();
+    for (size_t i = 0; i < nschool; i++)
+      if (out[i].radix_log == 1) {
+        NttSchedule s = out[i];
+        s.kara = 1;
+        out.push_back(s);
+      }
+  }
   g_detail = keep;
   return out;
 }
@@ -88,16 +100,16 @@ std::vector<NttSchedule> enumerate_schedules(int L, uint32_t logn, bool fw) {
 bool tune_db_best(const std::string& dev, int L, uint32_t logn, NttSchedule* out) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   // keep the latest measurement of each shape, then take the fastest
-  std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, float> last;
+  std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, uint32_t>, float> last;
   for (const TuneRow& r : g_rows)
     if (r.device == dev && (int)r.L == L && r.logn == logn)
-      last[std::make_tuple(r.tile_log, r.col_log, r.threads, r.radix_log)] = r.us;
+      last[std::make_tuple(r.tile_log, r.col_log, r.threads, r.radix_log, r.kara)] = r.us;
   if (last.empty()) return false;
   auto best = last.begin();
   for (auto it = last.begin(); it != last.end(); ++it)
     if (it->second < best->second) best = it;
   *out = NttSchedule{std::get<0>(best->first), std::get<1>(best->first), std::get<2>(best->first),
-                     std::get<3>(best->first)};
+                     std::get<3>(best->first), std::get<4>(best->first)};
   return true;
 }
 
@@ -201,7 +213,7 @@ static int tune(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t l
     rc = time_schedule(*p, cands[i], din, dout, opts.warmup, opts.reps, st, e0, e1, &us);
     if (rc) break;
     const NttSchedule& s = cands[i];
-    rows.push_back({dev, (uint32_t)L, p->logn, s.tile_log, s.col_log, s.threads, s.radix_log, us, opts.reps});
+    rows.push_back({dev, (uint32_t)L, p->logn, s.tile_log, s.col_log, s.threads, s.radix_log, us, opts.reps, s.kara});
     if (best < 0 || us < best_us) {
       best = (int)i;
       best_us = us;
@@ -229,7 +241,7 @@ static int tune(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t l
     if (!fw) g_rows.insert(g_rows.end(), rows.begin(), rows.end());
   }
   if (res) {
-    res->best = {chosen.tile_log, chosen.col_log, chosen.threads, chosen.radix_log};
+    res->best = {chosen.tile_log, chosen.col_log, chosen.threads, chosen.radix_log, chosen.kara};
     res->best_us = best_us;
     res->timed = (uint32_t)rows.size();
     res->feasible = feasible;
@@ -257,7 +269,7 @@ int moma_ntt_candidates(uint32_t limbs_compute, uint32_t log2_n, moma_ntt_schedu
   *count = (uint32_t)c.size();
   if (out)
     for (uint32_t i = 0; i < max && i < c.size(); i++)
-      out[i] = {c[i].tile_log, c[i].col_log, c[i].threads, c[i].radix_log};
+      out[i] = {c[i].tile_log, c[i].col_log, c[i].threads, c[i].radix_log, c[i].kara};
   return MOMA_OK;
 }
 
@@ -272,7 +284,7 @@ int moma_tune_db_get(uint32_t i, moma_tune_row_t* row) {
   const TuneRow& r = g_rows[i];
   row->limbs = r.L;
   row->log2_n = r.logn;
-  row->sched = {r.tile_log, r.col_log, r.threads, r.radix_log};
+  row->sched = {r.tile_log, r.col_log, r.threads, r.radix_log, r.kara};
   row->us = r.us;
   row->reps = r.reps;
   return MOMA_OK;
@@ -288,10 +300,10 @@ int moma_tune_db_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   FILE* f = fopen(path, "w");
   if (!f) return set_error(MOMA_E_ARG, std::string("cannot open ") + path);
-  fprintf(f, "device,limbs,log2_n,tile_log,col_log,threads,radix_log,us,reps\n");
+  fprintf(f, "device,limbs,log2_n,tile_log,col_log,threads,radix_log,us,reps,mul_variant\n");
   for (const TuneRow& r : g_rows)
-    fprintf(f, "%s,%u,%u,%u,%u,%u,%u,%.4f,%u\n", r.device.c_str(), r.L, r.logn, r.tile_log, r.col_log, r.threads,
-            r.radix_log, r.us, r.reps);
+    fprintf(f, "%s,%u,%u,%u,%u,%u,%u,%.4f,%u,%u\n", r.device.c_str(), r.L, r.logn, r.tile_log, r.col_log,
+            r.threads, r.radix_log, r.us, r.reps, r.kara);
   fclose(f);
   return MOMA_OK;
 }
@@ -310,8 +322,10 @@ int moma_tune_db_load(const char* path) {
     }
     char dev[128];
     TuneRow r;
-    if (sscanf(line, "%127[^,],%u,%u,%u,%u,%u,%u,%f,%u", dev, &r.L, &r.logn, &r.tile_log, &r.col_log, &r.threads,
-               &r.radix_log, &r.us, &r.reps) != 9) {
+    // rows written before the mul_variant column read as schoolbook
+    int got = sscanf(line, "%127[^,],%u,%u,%u,%u,%u,%u,%f,%u,%u", dev, &r.L, &r.logn, &r.tile_log, &r.col_log,
+                     &r.threads, &r.radix_log, &r.us, &r.reps, &r.kara);
+    if ((got != 9 && got != 10) || r.kara > 1) {
       fclose(f);
       return set_error(MOMA_E_ARG, std::string("malformed tuning row: ") + line);
     }

@@ -1,7 +1,8 @@
 """Build the tuning database, train the cost model on it, and measure its regret.
 
-  python -m paper_2501_07535_amd.tuning collect --db DB.csv --widths 64:1024:32 --logn 10:26
+  python -m paper_2501_07535_amd.tuning collect --db DB.csv --widths 64:1024:32 --logn 10:26 [--max-seconds S]
       exhaustive autotuning of every (bit-width class, size) shape, appended to DB.csv
+      (shapes already in DB.csv are skipped, so an interrupted collection resumes)
   python -m paper_2501_07535_amd.tuning evaluate --db DB.csv [DB2.csv ...] --out report.json --model cm.txt
       hold out shapes, train the model on the rest (on the GPU), and report the
       regret of timing only the model's top-k shapes against exhaustive search
@@ -41,7 +42,7 @@ def _rng_range(s: str):
     return list(range(a, b + 1, c[0] if c else 1))
 
 
-def collect(db: str, widths, logns, reps: int, warmup: int):
+def collect(db: str, widths, logns, reps: int, warmup: int, max_seconds: float = 0.0):
     import moma_inputs as mi
     import paper_2501_07535_amd as moma
     if os.path.exists(db):
@@ -54,6 +55,9 @@ def collect(db: str, widths, logns, reps: int, warmup: int):
         for logn in logns:
             if (L, logn) in done:
                 continue
+            if max_seconds and time.time() - t0 > max_seconds:
+                print(f"stopping after {time.time() - t0:.0f}s (--max-seconds); rerun to continue", flush=True)
+                return len(moma.tune_db_rows())
             n = 1 << logn
             r = moma.ntt_tune(f.q, f.root(n), n, L, reps=reps, warmup=warmup)
             print(f"[{time.time() - t0:7.1f}s] lam={lam} L={L} logn={logn} timed={r['timed']} "
@@ -69,8 +73,10 @@ def load_rows(paths):
         with open(p) as fh:
             next(fh)
             for line in fh:
-                dev, L, logn, tl, cl, th, rl, us, reps = line.strip().split(",")
-                rows.append((int(L), int(logn), (int(tl), int(cl), int(th), int(rl)), float(us)))
+                # device,limbs,log2_n,tile_log,col_log,threads,radix_log,us,reps[,mul_variant]
+                v = line.strip().split(",")
+                mv = int(v[9]) if len(v) > 9 else 0
+                rows.append((int(v[1]), int(v[2]), (int(v[3]), int(v[4]), int(v[5]), int(v[6]), mv), float(v[7])))
     # latest measurement of each (shape, schedule)
     last = {}
     for L, logn, s, us in rows:
@@ -212,6 +218,8 @@ def main():
     c.add_argument("--logn", default="10:26")
     c.add_argument("--reps", type=int, default=3)
     c.add_argument("--warmup", type=int, default=1)
+    c.add_argument("--max-seconds", type=float, default=0.0,
+                   help="stop before the next shape once this much time has passed (the database keeps what is done)")
     e = sub.add_parser("evaluate")
     e.add_argument("--db", nargs="+", required=True)
     e.add_argument("--out", required=True)
@@ -237,7 +245,7 @@ def main():
     elif a.cmd == "widths":
         widths(a.db, a.out, tuple(int(v) for v in a.logn.split(",")))
     elif a.cmd == "collect":
-        n = collect(a.db, _rng_range(a.widths), _rng_range(a.logn), a.reps, a.warmup)
+        n = collect(a.db, _rng_range(a.widths), _rng_range(a.logn), a.reps, a.warmup, a.max_seconds)
         print(f"database rows: {n}", flush=True)
     else:
         evaluate(a.db, a.out, a.model, epochs=a.epochs)

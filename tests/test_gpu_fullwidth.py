@@ -99,7 +99,7 @@ def test_full_width_batch_jobs():
 def test_full_width_sampled_schedules(lam, logn):
     """Radix-2 and radix-4 units (radix 4 up to 9 limbs), one and several
     passes, 4 to 32 columns: sampled launch shapes of the full-width kernels
-    against the oracle, and the radix-8 shapes refused."""
+    against the oracle; radix-8 shapes and the Karatsuba multiply refused."""
     import oracle
     import paper_2501_07535_amd as moma
     f = mi.find_prime(lam, 0, bits=lam)
@@ -110,7 +110,7 @@ def test_full_width_sampled_schedules(lam, logn):
     dx = to_dev(x)
     rng = random.Random(lam * 7 + logn)
     rmax = 2 if L <= 9 else 1  # the full-width kernels' register units
-    cands = [c for c in moma.ntt_candidates(L, logn) if c[3] <= rmax]
+    cands = [c for c in moma.ntt_candidates(L, logn) if c[3] <= rmax and c[4] == 0]
     rng.shuffle(cands)
     seen = set()
     for c in cands:
@@ -123,11 +123,13 @@ def test_full_width_sampled_schedules(lam, logn):
         y = moma.ntt_fwd(dx, q, w)
         assert (from_dev(y) == want).all(), c
         assert (from_dev(moma.ntt_inv(y, q, w)) == x).all(), c
-    for c in moma.ntt_candidates(L, logn):
-        if c[3] > rmax:
-            with pytest.raises(moma.MomaError):
-                moma.ntt_set_schedule(q, w, n, L, c)
-            break
+    # radix-8 shapes and the Karatsuba multiply are refused for a full-width modulus
+    refused = [c for c in moma.ntt_candidates(L, logn) if c[3] > rmax][:1] + \
+        [c for c in moma.ntt_candidates(L, logn) if c[4] == 1][:1]
+    assert refused
+    for c in refused:
+        with pytest.raises(moma.MomaError):
+            moma.ntt_set_schedule(q, w, n, L, c)
     moma.ntt_set_schedule(q, w, n, L, None)
 
 

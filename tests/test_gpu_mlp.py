@@ -18,7 +18,7 @@ def dev(a):
 
 
 def data(rows, seed):
-    x = mi.uniform01(rows * 6, 91, seed).reshape(rows, 6) * 4 - 2
+    x = mi.uniform01(rows * mi.MLP_IN, 91, seed).reshape(rows, mi.MLP_IN) * 4 - 2
     t = np.sin(x[:, 0]) + 0.3 * x[:, 1] * x[:, 2] + 0.1 * x.sum(axis=1)
     return x, t
 
@@ -34,7 +34,7 @@ def test_forward_matches_oracle(rows):
     import oracle
     import paper_2501_07535_amd as moma
     p = mi.mlp_init(11)
-    p[64 * 6:64 * 7] = 0.02
+    p[64 * mi.MLP_IN:64 * (mi.MLP_IN + 1)] = 0.02
     p32 = p.astype(np.float32).astype(np.float64)
     x, _ = data(rows, rows)
     x32 = x.astype(np.float32).astype(np.float64)
@@ -50,7 +50,7 @@ def test_gradient_matches_oracle(rows):
     import oracle
     import paper_2501_07535_amd as moma
     p = mi.mlp_init(12)
-    p[64 * 6:64 * 7] = 0.02
+    p[64 * mi.MLP_IN:64 * (mi.MLP_IN + 1)] = 0.02
     p32 = p.astype(np.float32).astype(np.float64)
     x, t = data(rows, 100 + rows)
     x32, t32 = x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)

@@ -12,28 +12,28 @@ NP = mi.MLP_NPARAM
 def split(p):
     o = 0
     out = []
-    for n in (64 * 6, 64, 64 * 64, 64, 64, 1):
+    for n in (64 * mi.MLP_IN, 64, 64 * 64, 64, 64, 1):
         out.append(p[o:o + n])
         o += n
     W1, b1, W2, b2, W3, b3 = out
-    return W1.reshape(64, 6), b1, W2.reshape(64, 64), b2, W3, b3
+    return W1.reshape(64, mi.MLP_IN), b1, W2.reshape(64, 64), b2, W3, b3
 
 
 def data(rows, seed):
-    x = mi.uniform01(rows * 6, 77, seed).reshape(rows, 6) * 4 - 2
+    x = mi.uniform01(rows * mi.MLP_IN, 77, seed).reshape(rows, mi.MLP_IN) * 4 - 2
     t = mi.uniform01(rows, 78, seed) * 3
     return x, t
 
 
 def test_nparams():
     import oracle
-    assert oracle.mlp_nparams() == NP == 4673
+    assert oracle.mlp_nparams() == NP == 64 * 7 + 64 + 64 * 64 + 64 + 64 + 1 == 4737
 
 
 def test_gradient_matches_central_differences():
     import oracle
     p = mi.mlp_init(1)
-    p[64 * 6:64 * 7] = 0.05            # small positive biases: fewer units sit exactly at the ReLU kink
+    p[64 * mi.MLP_IN:64 * (mi.MLP_IN + 1)] = 0.05            # small positive biases: fewer units sit exactly at the ReLU kink
     x, t = data(32, 1)
     g, loss = oracle.mlp_grad(p, x, t)
     idx = np.unique(np.concatenate([np.arange(NP - 70, NP), np.random.default_rng(0).integers(0, NP, 400)]))
@@ -49,9 +49,9 @@ def test_gradient_matches_central_differences():
 def test_all_active_network_is_a_matrix_product():
     import oracle
     rng = np.random.default_rng(2)
-    p = np.concatenate([rng.uniform(0.01, 0.2, 64 * 6), rng.uniform(0.1, 0.3, 64), rng.uniform(0.01, 0.05, 64 * 64),
+    p = np.concatenate([rng.uniform(0.01, 0.2, 64 * mi.MLP_IN), rng.uniform(0.1, 0.3, 64), rng.uniform(0.01, 0.05, 64 * 64),
                         rng.uniform(0.1, 0.3, 64), rng.uniform(-1, 1, 64), [0.7]])
-    x = rng.uniform(0.1, 2.0, (50, 6))
+    x = rng.uniform(0.1, 2.0, (50, mi.MLP_IN))
     W1, b1, W2, b2, W3, b3 = split(p)
     want = ((x @ W1.T + b1) @ W2.T + b2) @ W3 + b3
     assert np.allclose(oracle.mlp_forward(p, x), want, rtol=1e-13, atol=1e-13)

@@ -18,7 +18,20 @@ def test_load_rows_keeps_latest_measurement(tmp_path):
     _db(p, [("dev", 8, 12, 10, 5, 256, 2, 50.0, 3), ("dev", 8, 12, 10, 5, 256, 2, 40.0, 3),
             ("dev", 8, 12, 9, 4, 128, 1, 45.0, 3)])
     rows = sorted(tuning.load_rows([str(p)]))
-    assert rows == [(8, 12, (9, 4, 128, 1), 45.0), (8, 12, (10, 5, 256, 2), 40.0)]
+    assert rows == [(8, 12, (9, 4, 128, 1, 0), 45.0), (8, 12, (10, 5, 256, 2, 0), 40.0)]
+
+
+def test_load_rows_reads_the_multiply_variant_column(tmp_path):
+    """Rows with the mul_variant column keep it; rows without read as schoolbook."""
+    from paper_2501_07535_amd import tuning
+    p = tmp_path / "db.csv"
+    with open(p, "w") as fh:
+        fh.write("device,limbs,log2_n,tile_log,col_log,threads,radix_log,us,reps,mul_variant\n")
+        fh.write("dev,8,12,9,4,128,1,45.0,3,1\n")
+        fh.write("dev,8,12,9,4,128,1,41.0,3,0\n")
+        fh.write("dev,8,12,9,4,128,1,47.0,3\n")
+    rows = sorted(tuning.load_rows([str(p)]))
+    assert rows == [(8, 12, (9, 4, 128, 1, 0), 47.0), (8, 12, (9, 4, 128, 1, 1), 45.0)]
 
 
 def test_widths_report_best_time_and_doublings(tmp_path):
