@@ -233,7 +233,7 @@ int moma_ntt_describe(const uint32_t* q, const uint32_t* omega, uint64_t n, uint
  *   threads   - threads per workgroup, a multiple of 64 in [64, 1024];
  *   radix_log - stages each thread runs in registers per LDS round trip
  *               (radix 2, 4, 8 or 16; radix 16 up to 2 limbs, radix 8 up to 5,
- *               radix 4 up to 10; a full-width modulus: radix 4 up to 9);
+ *               radix 4 up to 16, also for a full-width modulus);
  *   mul_variant - how the butterfly's twiddle multiply forms its word
  *               products (Eq. (mulk)): MOMA_NTT_MUL_SCHOOLBOOK, or
  *               MOMA_NTT_MUL_KARATSUBA (one level of Karatsuba on the

@@ -22,16 +22,17 @@ constexpr int digit_stride(int L, bool fw = false) {  // table words per entry
 }
 
 // widest limb counts that get radix-4 / radix-8 / radix-16 register units
-constexpr int kMaxLimbsRadix4 = 10;
+// (radix 4 up to 16 limbs: 4 elements of 16 limbs plus the digit multiply fit
+// the 256 VGPRs of a lane at two waves per SIMD)
+constexpr int kMaxLimbsRadix4 = 16;
 constexpr int kMaxLimbsRadix8 = 5;
 constexpr int kMaxLimbsRadix16 = 2;
 // the Karatsuba form of the butterfly's multiply (Eq. (mulk)): radix-2 units,
 // 2 to 24 limbs (up to 768 bits, the widths its comparison with schoolbook
 // covers; its 2D - 1 live column sums cost registers the wider units lack)
 constexpr int kMaxLimbsKara = 24;
-// full-width moduli: radix-4 units up to 9 limbs (at 10 the digit multiply
-// takes one digit more and the unit no longer fits the register budget)
-constexpr int kMaxLimbsRadix4Fw = 9;
+// full-width moduli: radix-4 units up to 16 limbs as well
+constexpr int kMaxLimbsRadix4Fw = 16;
 
 // Constants of one modulus, sized for the largest limb count; the launchers copy
 // the first L words of each array into a compile-time sized kernel argument.

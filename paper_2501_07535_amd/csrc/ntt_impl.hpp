@@ -386,9 +386,9 @@ __device__ __forceinline__ void ntt_round_last(u32* lds, const TileGeo& t, u32 s
 // One tile of one pass: stages [K, K+k) on C = 2^logc groups of 2^k elements.
 // LDS holds the tile limb-planar: word (j * 2^k + u) * C + g is limb j of row u
 // of group g, so lanes with consecutive g touch consecutive banks.
-// the fused store keeps a unit's finished elements live while it stores them;
-// above 10 limbs that pushes the kernels into scratch memory (above 9 for a
-// full-width modulus, whose digit multiply at 10 limbs takes one digit more)
+// the fused store keeps a unit's finished elements live while it stores them
+// (up to 10 limbs, 9 for a full-width modulus: at 11 to 16 limbs it measured
+// no faster than the store from LDS)
 template <int L, bool FW = false>
 constexpr bool kFuseStore = L <= (FW ? 9 : 10);
 
@@ -602,6 +602,8 @@ __device__ __forceinline__ void pass_tile(u32* lds, const NttPassArgs& a, const 
   const u32 logn = a.logn;
   auto finish = [&](u32* x) { finish_elem<L, FW>(x, a, c); };
   // 4 elements of L limbs (and the scale multiply) stay in registers
+  // (up to 10 limbs: at 11 to 16 limbs the 4L live words cost occupancy, and
+  // 2^16-point transforms measured 3 to 10% slower)
   constexpr bool kVecStore = L <= (FW ? 9 : 10);
   if (kVecStore && t.K > 0 && vec_g) {
     // same addresses as the load: 4 consecutive groups of one row

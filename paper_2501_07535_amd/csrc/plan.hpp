@@ -57,7 +57,7 @@ extern thread_local std::string g_detail;
 int hip_fail(int e, const char* what);
 int build_field(const uint32_t* q, uint32_t limbs, std::shared_ptr<FieldEntry>* out);
 int get_plan(const uint32_t* q, const uint32_t* omega, uint64_t n, uint32_t limbs, std::shared_ptr<NttPlan>* out);
-// fw: a full-width modulus, whose kernels have radix-2 units, and radix-4 up to 9 limbs
+// fw: a full-width modulus, whose kernels have radix-2 and radix-4 units only
 uint32_t max_radix_log(int L, bool fw = false);
 int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>* out, bool fw = false);
 NttSchedule default_schedule(int L, uint32_t logn);

@@ -95,9 +95,9 @@ def test_full_width_batch_jobs():
     bt.close()
 
 
-@pytest.mark.parametrize("lam,logn", [(64, 13), (128, 14), (256, 12), (320, 11)])
+@pytest.mark.parametrize("lam,logn", [(64, 13), (128, 14), (256, 12), (320, 11), (512, 11)])
 def test_full_width_sampled_schedules(lam, logn):
-    """Radix-2 and radix-4 units (radix 4 up to 9 limbs), one and several
+    """Radix-2 and radix-4 units (radix 4 up to 16 limbs), one and several
     passes, 4 to 32 columns: sampled launch shapes of the full-width kernels
     against the oracle; radix-8 shapes and the Karatsuba multiply refused."""
     import oracle
@@ -109,7 +109,7 @@ def test_full_width_sampled_schedules(lam, logn):
     want = oracle.ntt_radix2(q, L, w, x)
     dx = to_dev(x)
     rng = random.Random(lam * 7 + logn)
-    rmax = 2 if L <= 9 else 1  # the full-width kernels' register units
+    rmax = 2 if L <= 16 else 1  # the full-width kernels' register units
     cands = [c for c in moma.ntt_candidates(L, logn) if c[3] <= rmax and c[4] == 0]
     rng.shuffle(cands)
     seen = set()

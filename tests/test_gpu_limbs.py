@@ -7,8 +7,10 @@ class width less four bits) runs a multi-pass forward and inverse transform
 under its default launch shape and under sampled feasible shapes of every
 register radix the limb count allows; whole vectors are compared with the
 oracle's radix-2 transforms.  L = 10 and 11 sit on the boundary of three
-kernel paths (the store fused into the last round, 16-byte stores, radix-4
-units: up to 10 limbs), so both get explicit shapes that take each path.
+kernel paths (the store fused into the last round and 16-byte stores, up to
+10 limbs; the radix-2 round that loads its second operand late, from 11
+limbs), L = 16 and 17 on that of the radix-4 units (up to 16 limbs), so these
+get explicit shapes that take each path.
 """
 import random
 
@@ -91,16 +93,16 @@ def test_every_compute_limb_count(L):
 # (tile_log, col_log, threads, radix_log) at n = 2^14, two or three passes:
 # 16 or 32 columns (later passes store from the last round's registers up to
 # 10 limbs), 4 or 8 columns (16-byte stores from LDS up to 10 limbs, one word
-# per lane above), radix-4 units (up to 10 limbs) and radix-2 units
+# per lane above), radix-4 units (up to 16 limbs) and radix-2 units
 BOUNDARY_SHAPES = [(10, 4, 256, 2), (10, 5, 256, 2), (10, 3, 256, 2), (10, 2, 128, 2),
-                   (10, 4, 256, 1), (10, 5, 512, 1), (10, 3, 256, 1), (10, 2, 128, 1)]
+                   (10, 4, 256, 1), (10, 5, 256, 1), (10, 3, 256, 1), (10, 2, 128, 1)]
 
 
-@pytest.mark.parametrize("L", [9, 10, 11, 12])
+@pytest.mark.parametrize("L", [9, 10, 11, 12, 16, 17])
 def test_kernel_path_boundary_limb_counts(L):
     ran = _check_shapes(L, 14, BOUNDARY_SHAPES, 501)
-    # radix-4 shapes are refused above 10 limbs; the radix-2 ones always run
-    assert ran == (8 if L <= 10 else 4)
+    # radix-4 shapes are refused above 16 limbs; the radix-2 ones always run
+    assert ran == (8 if L <= 16 else 4)
 
 
 @pytest.mark.parametrize("logn,nsamp", [(25, 6), (26, 4)])

@@ -5,7 +5,7 @@ import math
 
 import pytest
 
-MAX_RADIX = {**{L: 4 for L in range(1, 3)}, **{L: 3 for L in range(3, 6)}, **{L: 2 for L in range(6, 11)}, **{L: 1 for L in range(11, 33)}}
+MAX_RADIX = {**{L: 4 for L in range(1, 3)}, **{L: 3 for L in range(3, 6)}, **{L: 2 for L in range(6, 17)}, **{L: 1 for L in range(17, 33)}}
 
 
 def _max_threads(L, r):
