@@ -43,23 +43,44 @@ def word_products(L: int) -> int:
 
 
 def issue_costs(rates: dict) -> tuple[float, float]:
-    """Full-rate issue slots of one word product with its carry step (a
-    v_mad_u64_u32 whose carry-out feeds a v_addc_co_u32) and of one add-class
-    op (an add or subtract with carry), from the measured issue rates."""
-    return 2.0 * rates["add_u32"] / rates["mad_addc_u32"], rates["add_u32"] / rates["add_co_addc_u32"]
+    """Cost of one word product with its carry step (a v_mad_u64_u32 whose
+    carry-out feeds a v_addc_co_u32) and of one add-class op (an add or
+    subtract with carry), in peak lane-ops: the time the instructions take at
+    their measured issue rates, times PEAK_INT_OPS.  Work priced this way and
+    divided by PEAK_INT_OPS is the time the work takes at the measured rates,
+    so achieved / peak is that time over the measured time."""
+    return 2.0 * PEAK_INT_OPS / rates["mad_addc_u32"], PEAK_INT_OPS / rates["add_co_addc_u32"]
+
+
+def multiply_forms(L: int, rates: dict) -> dict:
+    """Work of one L-limb Montgomery multiply in peak lane-ops, in its two
+    gfx950 forms.  Word form: P(L) 32-bit word products, each a v_mad_u64_u32
+    plus the v_addc_co_u32 that takes its carry.  Digit form (the same
+    multiply on D digits of b bits, b = 29 up to 28 limbs, else 28, D =
+    ceil((32L - 2) / b)): 2D^2 digit products, each one v_mad_u64_u32 and no
+    carry step (a column of them stays below 2^64), one v_mul_lo_u32 per
+    reduction digit, and two add-class ops per column (shift and mask)."""
+    cm, ca = issue_costs(rates)
+    b = 29 if L <= 28 else 28
+    D = -(-(32 * L - 2) // b)
+    word = word_products(L) * cm
+    digit = (2 * D * D * PEAK_INT_OPS / rates["mad_u64_u32"] + D * PEAK_INT_OPS / rates["mul_lo_u32"]
+             + 2 * (2 * D - 1) * ca)
+    return {"word": word, "digit": digit, "digits": D}
 
 
 def butterfly_slots(L: int, rates: dict) -> float:
-    """Issue slots of one butterfly under the op model: one L-limb Montgomery
-    multiply (P(L) word products, each with its carry step) plus a modular add
-    and a modular subtract (3L add-class ops each: the chain, the trial
-    subtraction, the select)."""
+    """Work of one butterfly under the op model, in peak lane-ops: one L-limb
+    Montgomery multiply in the cheaper of its two forms (multiply_forms) plus
+    a modular add and a modular subtract (3L add-class ops each: the chain,
+    the trial subtraction, the select)."""
     cm, ca = issue_costs(rates)
-    return word_products(L) * cm + 6 * L * ca
+    f = multiply_forms(L, rates)
+    return min(f["word"], f["digit"]) + 6 * L * ca
 
 
 def blas_slots(op: str, L: int, rates: dict, karatsuba: bool = False) -> float:
-    """Issue slots per element of one BLAS op under the same op model.  vmul
+    """Work per element of one BLAS op under the same op model, in peak lane-ops.  vmul
     (Barrett): two full L x L products (3 ceil(L/2)^2 word products each by
     Karatsuba, else L^2) and the low half of r2 * q (L(L+1)/2), plus 3L for the
     subtraction and correction; axpy: a Montgomery multiply by alpha (P(L))
@@ -228,7 +249,7 @@ def blas(args):
             t_hbm, t_alu = byt / PEAK_HBM, slots / PEAK_INT_OPS
             bound = "hbm" if t_hbm >= t_alu else "alu"
             print(json.dumps({"op": op, "lambda": lam, "limbs": L, "log2_n": args.blas_logn, "us": round(us, 2),
-                              "GB_s": round(byt / us / 1e3, 1), "Tslots_s": round(slots / us / 1e6, 3),
+                              "GB_s": round(byt / us / 1e3, 1), "Tops_s": round(slots / us / 1e6, 3),
                               "bound": bound, "roofline_us": round(max(t_hbm, t_alu) * 1e6, 2),
                               "frac": round(max(t_hbm, t_alu) * 1e6 / us, 4),
                               "hbm_frac": round(t_hbm * 1e6 / us, 4), "alu_frac": round(t_alu * 1e6 / us, 4),
@@ -305,8 +326,10 @@ def peaks():
                                                                      "mad_addc_u32", "mul_lo_u32", "mul_hi_u32")},
            "hbm_TBs": {"copy": round(r["hbm_copy"] / 1e12, 3), "triad": round(r["hbm_triad"] / 1e12, 3)},
            "of_hbm_peak": {"copy": round(r["hbm_copy"] / PEAK_HBM, 4), "triad": round(r["hbm_triad"] / PEAK_HBM, 4)},
-           "slots_per_word_product_with_carry": round(cm, 4), "slots_per_add_op": round(ca, 4),
-           "slots_per_butterfly": {str(L): round(butterfly_slots(L, r), 1) for L in (2, 4, 8, 12, 16, 24, 32)},
+           "lane_ops_per_word_product_with_carry": round(cm, 4), "lane_ops_per_add_op": round(ca, 4),
+           "lane_ops_multiply": {str(L): {k: round(v, 1) for k, v in multiply_forms(L, r).items()}
+                                 for L in (2, 4, 8, 12, 16, 24, 32)},
+           "lane_ops_per_butterfly": {str(L): round(butterfly_slots(L, r), 1) for L in (2, 4, 8, 12, 16, 24, 32)},
            "compute_units": r["compute_units"]}
     print(json.dumps(out), flush=True)
 
@@ -412,6 +435,7 @@ def main():
         # wave instructions x 4 cycles each over the SIMD-cycles of one launch
         valu_issue = counters["sq_insts_valu_per_launch"] * 4 / (VALU_SIMDS * CLOCK_HZ * launch_ms * 1e-3)
     cm, ca = issue_costs(rates)
+    mf = multiply_forms(L, rates)
 
     if args.calib_copy_mib:
         src = torch.zeros(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
@@ -459,10 +483,13 @@ def main():
                      "launches_per_step": launches,
                      "avg_launch_us": round(launch_ms * 1e3, 3),
                      "avg_launch_us_from": "HIP events over the timed region / launches",
-                     "op_model": {"word_products_per_butterfly": word_products(L),
+                     "op_model": {"word_products_per_multiply": word_products(L),
+                                  "digit_products_per_multiply": 2 * mf["digits"] ** 2,
+                                  "lane_ops_multiply_word_form": round(mf["word"], 2),
+                                  "lane_ops_multiply_digit_form": round(mf["digit"], 2),
                                   "add_class_ops_per_butterfly": 6 * L,
-                                  "slots_per_word_product": round(cm, 4), "slots_per_add_op": round(ca, 4),
-                                  "slots_per_butterfly": round(slots, 2)},
+                                  "lane_ops_per_add_op": round(ca, 4),
+                                  "lane_ops_per_butterfly": round(slots, 2)},
                      "measured_rates_Tops": {k: round(rates[k] / 1e12, 3) for k in
                                              ("add_u32", "add_co_addc_u32", "mad_u64_u32", "mad_addc_u32",
                                               "mul_lo_u32", "mul_hi_u32")},
