@@ -230,9 +230,16 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
     u32 lb = v >> (k - sg0 - R);
     u32 p0 = lb * B + (v & (sub - 1));
     u32 x[1 << R][L];
+    // LOADG: the first stage's twiddle (one per unit) is loaded before the
+    // elements, and the elements pair by pair of the first stage, (e, e +
+    // 2^(R-1)): a wave's loads complete in issue order, so the first pair's
+    // butterfly can start while the later pairs are still in flight
+    u32 w0[LOADG ? digit_stride(L, FW) : 1];
     if constexpr (LOADG) {
+      if constexpr (!FIRST) load_digits<L, FW>(w0, tw + tw_pos(t, sg0, lb, g) * digit_stride(L, FW));
 #pragma unroll
-      for (int e = 0; e < (1 << R); e++) {
+      for (int pp = 0; pp < (1 << R); pp++) {
+        const int e = (pp >> 1) + (pp & 1) * (1 << (R - 1));
         const u32 u = p0 + e * sub;  // LDS row; global row u (first pass) or rev(u) (later passes)
         const u64 src = (t.K == 0) ? (u64)u * t.S + t.o0 + g
                                    : (t.ro << (t.K + k)) + ((u64)rev_bits(u, k) << t.K) + t.b0 + g;
@@ -252,21 +259,26 @@ __device__ __forceinline__ void ntt_round(u32* lds, const TileGeo& t, u32 sg0, c
       for (int p = 0; p < (1 << (R - 1)); p++) {
         // p with a zero bit inserted at position kb: the pair (e, e + half) of this stage
         const int e = ((p >> kb) << (kb + 1)) | (p & (half - 1));
-        if (FIRST && (e >> (R - s)) == 0) {
-          if constexpr (FW)
-            ct_butterfly_one_fw<L>(x[e], x[e + half], q2v);
-          else
-            ct_butterfly_one<L>(x[e], x[e + half], q2v);
-        } else {
-          u32 lbk = (lb << s) + (u32)(e >> (R - s));
-          u32 w[digit_stride(L, FW)];
-          load_digits<L, FW>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L, FW));
+        auto bfly = [&](const u32* w) {
           if constexpr (FW)
             ct_butterfly_fw<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
           else if constexpr (AR == kArithKara)
             ct_butterfly_kara<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
           else
             ct_butterfly_digits<L>(x[e], x[e + half], w, c.qd, c.qinvd, q2v);
+        };
+        if (FIRST && (e >> (R - s)) == 0) {
+          if constexpr (FW)
+            ct_butterfly_one_fw<L>(x[e], x[e + half], q2v);
+          else
+            ct_butterfly_one<L>(x[e], x[e + half], q2v);
+        } else if (LOADG && s == 0) {
+          bfly(w0);  // stage 0: every pair of the unit has block lb
+        } else {
+          u32 lbk = (lb << s) + (u32)(e >> (R - s));
+          u32 w[digit_stride(L, FW)];
+          load_digits<L, FW>(w, tw + tw_pos(t, sg0 + s, lbk, g) * digit_stride(L, FW));
+          bfly(w);
         }
       }
     }
