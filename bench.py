@@ -371,7 +371,22 @@ def main():
     stream = torch.cuda.current_stream()
     default_sched = moma.ntt_get_schedule(q, w, n, L)
     default_us = None if args.forward_only else _time_fwd(moma, torch, stream, dx, dy, q, w, 3, 20)
+    def settle(seconds):
+        """Untimed transforms for `seconds`: the GPU's clock ramps up over tens
+        of milliseconds of sustained work, and drops again in idle gaps."""
+        k = 0
+        t0 = time.time()
+        while time.time() - t0 < seconds:
+            moma.ntt_fwd(dx, q, w, out=dy)
+            k += 1
+            if k % 32 == 0:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        return k
+
     tuned = None
+    # the autotuner's timings, too, should see the steady clock
+    settle_tune_n = 0 if args.schedule or args.no_tune else settle(args.settle)
     if args.schedule:
         moma.ntt_set_schedule(q, w, n, L, tuple(int(v) for v in args.schedule.split(",")))  # 4 or 5 fields
     elif not args.no_tune:
@@ -381,18 +396,10 @@ def main():
     launches = plan["passes"]
 
     # Clock settle: after the autotuner's timings (short runs with host
-    # synchronisations between them) the GPU's clock ramps up over tens of
-    # milliseconds of sustained work, so untimed transforms run for
-    # args.settle seconds before the W warm-up steps and the timed steps see
-    # the steady clock.
-    settle_n = 0
-    t_settle = time.time()
-    while time.time() - t_settle < args.settle:
-        moma.ntt_fwd(dx, q, w, out=dy)
-        settle_n += 1
-        if settle_n % 32 == 0:
-            torch.cuda.synchronize()
-    torch.cuda.synchronize()
+    # synchronisations between them) the clock is low again, so untimed
+    # transforms run for args.settle seconds before the W warm-up steps and
+    # the timed steps see the steady clock.
+    settle_n = settle(args.settle)
 
     for _ in range(args.warmup):
         moma.ntt_fwd(dx, q, w, out=dy)
@@ -515,7 +522,8 @@ def main():
                      "schedule": list(moma.ntt_get_schedule(q, w, n, L))},
         "cpu_baseline": cpu,
         "extras": {"fwd_us": round(ms_step * 1e3, 3), "inv_us": round(ms_inv * 1e3, 3) if ms_inv else None,
-                   "clock_settle": {"seconds": args.settle, "untimed_transforms": settle_n},
+                   "clock_settle": {"seconds": args.settle, "untimed_transforms": settle_n,
+                                    "before_autotuning": settle_tune_n},
                    "default_schedule": list(default_sched),
                    "default_schedule_fwd_us": round(default_us, 3) if default_us else None,
                    "autotuned": tuned,
