@@ -174,8 +174,10 @@ def sweep(args):
         dx = torch.from_numpy(mi.to_planar(x).view(np.int32)).to(dev)
         dy = torch.empty_like(dx)
         moma.ntt_prepare(q, w, n, L)
+        _settle_fwd(moma, torch, dx, dy, q, w, args.settle)
         tuned = moma.ntt_tune(q, w, n, L, reps=3, warmup=1)
         steps = max(3, min(50, int(2e5 / max(tuned["best_us"], 1.0))))
+        _settle_fwd(moma, torch, dx, dy, q, w, args.settle)
         us = _time_fwd(moma, torch, stream, dx, dy, q, w, 2, steps)
         ks = np.array([0, 1, n - 1], dtype=np.int64)
         got = mi.from_planar(dy[:, torch.from_numpy(ks).to(dev)].cpu().numpy().view(np.uint32))
@@ -372,17 +374,7 @@ def main():
     default_sched = moma.ntt_get_schedule(q, w, n, L)
     default_us = None if args.forward_only else _time_fwd(moma, torch, stream, dx, dy, q, w, 3, 20)
     def settle(seconds):
-        """Untimed transforms for `seconds`: the GPU's clock ramps up over tens
-        of milliseconds of sustained work, and drops again in idle gaps."""
-        k = 0
-        t0 = time.time()
-        while time.time() - t0 < seconds:
-            moma.ntt_fwd(dx, q, w, out=dy)
-            k += 1
-            if k % 32 == 0:
-                torch.cuda.synchronize()
-        torch.cuda.synchronize()
-        return k
+        return _settle_fwd(moma, torch, dx, dy, q, w, seconds)
 
     tuned = None
     # the autotuner's timings, too, should see the steady clock
@@ -636,6 +628,20 @@ def cyclic_product(moma, torch, stream, da, db, dc, q, w, n, warmup, reps):
     res["fused_speedup"] = round(res["unfused_us"] / res["fused_us"], 3)
     del ta, tb, shift
     return res
+
+
+def _settle_fwd(moma, torch, dx, dy, q, w, seconds):
+    """Untimed forward transforms for `seconds` (the GPU clock ramps up over
+    tens of milliseconds of sustained work and drops in idle gaps)."""
+    k = 0
+    t0 = time.time()
+    while time.time() - t0 < seconds:
+        moma.ntt_fwd(dx, q, w, out=dy)
+        k += 1
+        if k % 32 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return k
 
 
 def _time_fwd(moma, torch, stream, dx, dy, q, w, warmup, reps):
