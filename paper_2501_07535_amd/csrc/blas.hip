@@ -152,7 +152,11 @@ __global__ __launch_bounds__(256) void blas_batch_kernel(const BlasJobRec* __res
   const u32 w = blockIdx.x;
   if (w >= nitems) return;
   const uint2 it = items[w];
-  const BlasJobRec r = recs[it.x];
+  const BlasJobRec* rec = recs + it.x;
+  BlasJobRec r = *rec;
+  r.a = load_global_ptr(&rec->a);
+  r.b = load_global_ptr(&rec->b);
+  r.out = load_global_ptr(&rec->out);
   const BlasC<L> c = consts[it.x];
   const u64 i = (u64)it.y * blockDim.x + threadIdx.x;
   if (i >= r.n) return;

@@ -37,6 +37,18 @@ namespace moma {
 typedef uint32_t u32;
 typedef uint64_t u64;
 
+// A pointer that a kernel reads from memory (a batch record) is generic to the
+// compiler, which then accesses it with flat loads and stores.  Those count on
+// the LDS wait counter as well, so every wait for an LDS access also waits for
+// the HBM accesses in flight.  The records hold device global addresses:
+// reading the field as a global-space pointer lets the compiler use global
+// loads and stores wherever the pointer goes.
+template <class T>
+__device__ __forceinline__ T* load_global_ptr(T* const* slot) {
+  typedef __attribute__((address_space(1))) T* GlobalPtr;
+  return (T*)*static_cast<const GlobalPtr*>(static_cast<const void*>(slot));
+}
+
 // ----------------------------------------------------------------- word ops
 
 // acc(64) += x * y; hi += carry-out.  x in a VGPR, y in a VGPR.

@@ -724,7 +724,12 @@ __global__ __launch_bounds__((PassTraits<L, R>::max_threads)) void ntt_batch_ker
   const u32 i = blockIdx.x;
   if (i >= nitems) return;
   const uint2 it = items[i];
-  const NttPassArgs a = passes[it.x];
+  const NttPassArgs* rec = passes + it.x;
+  NttPassArgs a = *rec;
+  a.in = load_global_ptr(&rec->in);
+  a.in2 = load_global_ptr(&rec->in2);
+  a.out = load_global_ptr(&rec->out);
+  a.tw = load_global_ptr(&rec->tw);
   const NttC<L, FW> c = consts[it.x];
   pass_tile<L, R, MUL, LASTX, FW ? kArithFull : kArithLazy>(lds, a, c, it.y);
 }
