@@ -126,7 +126,8 @@ def parse():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="time the default schedule without autotuning")
     ap.add_argument("--settle", type=float, default=0.25,
-                    help="seconds of untimed transforms before the warm-up steps (the clock's ramp)")
+                    help="seconds of untimed transforms before the autotuner, before the warm-up steps and before "
+                         "timing each steady-state batch (the clock's ramp)")
     ap.add_argument("--schedule", default=None,
                     help="tile_log,col_log,threads,radix_log[,mul_variant]: use this launch shape instead of "
                          "autotuning")
@@ -187,7 +188,7 @@ def sweep(args):
         kmax = max(1, min(64, (16 << 30) // per))
         kmax = 1 << (kmax.bit_length() - 1)
         st = steady_state(moma, torch, stream, dx, q, w, n, L, logn,
-                          ks=tuple(sorted({k for k in (1, 4, 16, 64) if k <= kmax} | {kmax})))
+                          ks=tuple(sorted({k for k in (1, 4, 16, 64) if k <= kmax} | {kmax})), settle=args.settle)
         B = n // 2 * logn
         print(json.dumps({"lambda": lam, "limbs": L, "q_bits": q.bit_length(), "full_width": bool(bits),
                           "log2_n": logn, "fwd_us": round(us, 2),
@@ -462,7 +463,7 @@ def main():
 
     steady = None
     if not args.no_batch:
-        steady = steady_state(moma, torch, stream, dx, q, w, n, L, logn)
+        steady = steady_state(moma, torch, stream, dx, q, w, n, L, logn, settle=args.settle)
 
     batch = None
     if not args.no_batch:
@@ -515,7 +516,7 @@ def main():
         "cpu_baseline": cpu,
         "extras": {"fwd_us": round(ms_step * 1e3, 3), "inv_us": round(ms_inv * 1e3, 3) if ms_inv else None,
                    "clock_settle": {"seconds": args.settle, "untimed_transforms": settle_n,
-                                    "before_autotuning": settle_tune_n},
+                                    "before_autotuning": settle_tune_n, "before_each_steady_state_batch": True},
                    "default_schedule": list(default_sched),
                    "default_schedule_fwd_us": round(default_us, 3) if default_us else None,
                    "autotuned": tuned,
@@ -656,10 +657,25 @@ def _time_fwd(moma, torch, stream, dx, dy, q, w, warmup, reps):
     return e0.elapsed_time(e1) * 1e3 / reps
 
 
-def steady_state(moma, torch, stream, dx, q, w, n, L, logn, ks=(1, 2, 4, 8, 16, 32, 64)):
+def _settle_batch(torch, b, seconds):
+    """Untimed runs of a batch for `seconds`, as _settle_fwd for single calls:
+    building the batch leaves the GPU idle and its clock low."""
+    k = 0
+    t0 = time.time()
+    while time.time() - t0 < seconds:
+        b.run()
+        k += 1
+        if k % 8 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return k
+
+
+def steady_state(moma, torch, stream, dx, q, w, n, L, logn, ks=(1, 2, 4, 8, 16, 32, 64), settle=0.0):
     """The paper's steady-state protocol (Section 5.1): t_single = t_all / k for a
     batch of k transforms of this size, minimised over k; here each batch is one
-    graph launch of the batched executor over k independent buffers."""
+    graph launch of the batched executor over k independent buffers, timed after
+    `settle` seconds of untimed runs of the same batch."""
     outs = [torch.empty_like(dx) for _ in range(max(ks))]
     ins = [dx.clone() for _ in range(max(ks))]
     res = {}
@@ -667,6 +683,7 @@ def steady_state(moma, torch, stream, dx, q, w, n, L, logn, ks=(1, 2, 4, 8, 16, 
         b = moma.Batch([(ins[i], outs[i], q, w, False) for i in range(k)])
         b.run()
         torch.cuda.synchronize()
+        _settle_batch(torch, b, settle)
         reps = max(3, 32 // k)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)

@@ -12,8 +12,11 @@
 // decreasing work, one workgroup per item (the dispatcher starts the largest
 // tiles first).  Phases follow one
 // another in stream order, which is the only dependency between a job's
-// passes.  The launches are captured once into a graph; running the batch is
-// one hipGraphLaunch.
+// passes.  Jobs whose data is 16 MiB or more run in groups instead: the jobs
+// of a group share phases, and each group's phases follow the previous
+// group's, so that the passes of a group revisit at most 256 MiB of data (one
+// job if it is larger).  The launches are captured once into a graph; running
+// the batch is one hipGraphLaunch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -155,6 +158,10 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     std::vector<uint2> items;
   };
   std::map<std::tuple<int, int, uint32_t, bool>, BGroup> bgroups;
+  // groups of large jobs: the phases [group_phase, group_phase + group_span)
+  constexpr uint64_t kGroupMinJobBytes = 16ull << 20, kGroupBytes = 256ull << 20;
+  uint32_t group_phase = 0, group_span = 0;
+  uint64_t group_bytes = 0;
   for (uint32_t j = 0; j < njobs; j++) {
     const moma_ntt_job_t& job = jobs[j];
     const std::string tag = "job " + std::to_string(j) + ": ";
@@ -228,6 +235,21 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       g_detail = keep;
     }
     const size_t plane_words = (size_t)p->n * f.L;
+    uint32_t ph0 = 0;
+    {
+      const uint32_t copies = job.kind == MOMA_JOB_CYCLIC_MUL ? 2u : 1u;
+      const uint64_t bytes = (uint64_t)plane_words * sizeof(uint32_t) * copies;
+      if (bytes >= kGroupMinJobBytes) {
+        if (group_bytes > 0 && group_bytes + bytes > kGroupBytes) {
+          group_phase += group_span;
+          group_span = 0;
+          group_bytes = 0;
+        }
+        ph0 = group_phase;
+        group_bytes += bytes;
+        group_span = std::max(group_span, (uint32_t)passes.size() * copies);
+      }
+    }
     auto alloc = [&](size_t words, uint32_t** outp) -> int {
       void* s = nullptr;
       if (hipMalloc(&s, words * sizeof(uint32_t))) return set_error(MOMA_E_NOMEM, tag + "job buffers");
@@ -240,9 +262,10 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       int r = alloc(2 * plane_words, &sa);
       if (r) return r;
       uint32_t* sb = sa + plane_words;
-      add(*p, sched, passes, p->fwd, none, false, job.d_in, nullptr, sa, sa, 0);
-      add(*p, sched, passes, p->fwd, none, false, job.d_in2, nullptr, sb, sb, 0);
-      add(*p, sched, passes, p->inv, p->mul_consts, true, sa, sb, job.d_out, job.d_out, (uint32_t)passes.size());
+      add(*p, sched, passes, p->fwd, none, false, job.d_in, nullptr, sa, sa, ph0);
+      add(*p, sched, passes, p->fwd, none, false, job.d_in2, nullptr, sb, sb, ph0);
+      add(*p, sched, passes, p->inv, p->mul_consts, true, sa, sb, job.d_out, job.d_out,
+          ph0 + (uint32_t)passes.size());
       if (f.Ls > f.L) b.fills.push_back({job.d_out, p->n, f.L, f.Ls});
       continue;
     }
@@ -253,7 +276,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       if (r) return r;
     }
     add(*p, sched, passes, inverse ? p->inv : p->fwd, inverse ? p->inv_consts : none, inverse, job.d_in, nullptr,
-        first_out, job.d_out, 0);
+        first_out, job.d_out, ph0);
     if (f.Ls > f.L && job.d_out != job.d_in) b.fills.push_back({job.d_out, p->n, f.L, f.Ls});
   }
   // upload tables and build the launch list, phase by phase

@@ -45,6 +45,60 @@ def test_batch_mixed_jobs_match_plain_and_oracle():
     b.close()
 
 
+def test_batch_large_jobs_run_in_groups():
+    """Jobs of 16 MiB or more run in groups of at most 256 MiB of data, one group
+    after another: eight 2^20-point 256-bit transforms (32 MiB each; forward,
+    inverse and in place) fill the first group, a ninth and a cyclic product of
+    two 2^19-point vectors the second, and small jobs run beside the first.
+    Every output equals the plain call's, sampled outputs the oracle's
+    definition, and a second run the first."""
+    import oracle
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(256, 0)
+    L, q = f.limbs, f.q
+    big, half, small = 1 << 20, 1 << 19, 1 << 12
+    wb, wh, ws = f.root(big), f.root(half), f.root(small)
+    specs, checks, host = [], [], []
+    for k in range(9):
+        xh = mi.residues(f, big, L, 71, k)
+        x = to_dev(xh)
+        inv, inplace = k % 3 == 1, k == 5
+        o = x.clone() if inplace else torch.empty_like(x)
+        checks.append((o, (moma.ntt_inv if inv else moma.ntt_fwd)(x, q, wb), not inplace))
+        specs.append((o if inplace else x, o, q, wb, inv))
+        host.append((xh, inv))
+    a, bv = to_dev(mi.residues(f, half, L, 72, 0)), to_dev(mi.residues(f, half, L, 72, 1))
+    o = torch.empty_like(a)
+    checks.append((o, moma.ntt_cyclic_mul(a, bv, q, wh), True))
+    specs.append(((a, bv), o, q, wh, moma.JOB_CYCLIC_MUL))
+    for k in range(6):
+        x = to_dev(mi.residues(f, small, L, 73, k))
+        o = torch.empty_like(x)
+        checks.append((o, moma.ntt_fwd(x, q, ws), True))
+        specs.append((x, o, q, ws, False))
+    torch.cuda.synchronize()
+    say("batch: nine 2^20-point jobs, a 2^19-point cyclic product, six 2^12-point jobs")
+    b = moma.Batch(specs)
+    assert b.info()["launches"] >= 8  # two groups of at least four passes each
+    b.run()
+    torch.cuda.synchronize()
+    for i, (o, want, _) in enumerate(checks):
+        assert torch.equal(o, want), i
+    ks = np.array([0, 1, 777, big - 1], dtype=np.int64)
+    for k in (0, 1, 8):  # one forward and one inverse job of the first group, one job of the second
+        xh, inv = host[k]
+        got = from_dev(checks[k][0][:, torch.from_numpy(ks).to("cuda:0")].contiguous())
+        want = (oracle.intt_direct if inv else oracle.ntt_direct)(q, L, wb, xh, ks)
+        assert (got == want).all(), k
+    first = [o.clone() for o, _, _ in checks]
+    b.run()
+    torch.cuda.synchronize()
+    for i, (o, _, rerun_same) in enumerate(checks):
+        if rerun_same:
+            assert torch.equal(o, first[i]), i
+    b.close()
+
+
 def test_batch_shape_recipe():
     shapes = [mi.batch_shape(i) for i in range(4096)]
     lams = {s[0] for s in shapes}
