@@ -164,14 +164,17 @@ int plan_passes(int L, uint32_t logn, const NttSchedule& s, std::vector<NttPass>
 }
 
 // First feasible of an ordered list of (tile_log, col_log), with the radix
-// and thread count filled in by rule: radix 4 up to 10 limbs, and enough
-// threads to give each one or two units per round.  (From 11 limbs a radix-4
-// unit holds the lane at 3 waves per SIMD, 2 from 13; it pays for large lone
-// transforms, which the tuner and the cost model find, but not for the small
-// jobs of a batch: 4096-job batch 7.50 ms against 7.32 ms with radix 2.)
-constexpr int kRuleMaxLimbsRadix4 = 10;
-static NttSchedule first_feasible(int L, uint32_t logn, const std::vector<std::pair<uint32_t, uint32_t>>& shapes) {
-  uint32_t radix = std::min(L <= kRuleMaxLimbsRadix4 ? 2u : 1u, max_radix_log(L));
+// and thread count filled in by rule: radix 4 up to max_limbs_radix4 limbs,
+// and enough threads to give each one or two units per round.  (From 11 limbs
+// a radix-4 unit holds the lane at 3 waves per SIMD, 2 from 13.  For a lone
+// transform the fixed rule stays at radix 2 there, and the tuner and the cost
+// model find where radix 4 pays.  Inside a batch, where other jobs fill the
+// chip, 12-limb jobs take radix 4: the 4096-job batch ran 6.78 ms against
+// 6.89 ms with radix 2.)
+constexpr int kRuleMaxLimbsRadix4 = 10, kBatchMaxLimbsRadix4 = 12;
+static NttSchedule first_feasible(int L, uint32_t logn, const std::vector<std::pair<uint32_t, uint32_t>>& shapes,
+                                  int max_limbs_radix4 = kRuleMaxLimbsRadix4) {
+  uint32_t radix = std::min(L <= max_limbs_radix4 ? 2u : 1u, max_radix_log(L));
   std::string keep = g_detail;
   NttSchedule last{};
   for (auto tc : shapes) {
@@ -219,7 +222,7 @@ NttSchedule batch_schedule(int L, uint32_t logn) {
   for (uint32_t cl : {5u, 4u}) shapes.push_back({t64, cl});
   for (uint32_t cl : {5u, 4u, 3u, 2u}) shapes.push_back({t32, cl});
   for (uint32_t cl : {3u, 2u, 1u}) shapes.push_back({t64, cl});
-  return first_feasible(L, logn, shapes);
+  return first_feasible(L, logn, shapes, kBatchMaxLimbsRadix4);
 }
 
 NttSchedule initial_schedule(int L, uint32_t logn, bool fw) {
