@@ -99,6 +99,31 @@ def test_batch_large_jobs_run_in_groups():
     b.close()
 
 
+def test_batch_jobs_larger_than_a_group():
+    """A job of more than 256 MiB makes a group of its own: two 2^24-point
+    256-bit transforms (512 MiB each, one forward, one inverse in place) run
+    one after the other in one batch, beside a 2^20-point job; every output
+    equals the plain call's."""
+    import paper_2501_07535_amd as moma
+    f = mi.find_prime(256, 0)
+    L, q = f.limbs, f.q
+    n, m = 1 << 24, 1 << 20
+    wn, wm = f.root(n), f.root(m)
+    x0 = to_dev(mi.residues(f, n, L, 74, 0))
+    x1 = to_dev(mi.residues(f, n, L, 74, 1))
+    x2 = to_dev(mi.residues(f, m, L, 74, 2))
+    o0, o2 = torch.empty_like(x0), torch.empty_like(x2)
+    want = [moma.ntt_fwd(x0, q, wn), moma.ntt_inv(x1, q, wn), moma.ntt_fwd(x2, q, wm)]
+    torch.cuda.synchronize()
+    say("batch: two 2^24-point jobs of 512 MiB and a 2^20-point job")
+    b = moma.Batch([(x0, o0, q, wn, False), (x1, x1, q, wn, True), (x2, o2, q, wm, False)])
+    b.run()
+    torch.cuda.synchronize()
+    for i, got in enumerate((o0, x1, o2)):
+        assert torch.equal(got, want[i]), i
+    b.close()
+
+
 def test_batch_shape_recipe():
     shapes = [mi.batch_shape(i) for i in range(4096)]
     lams = {s[0] for s in shapes}
