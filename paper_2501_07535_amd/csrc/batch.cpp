@@ -16,7 +16,8 @@
 // of a group share phases, and each group's phases follow the previous
 // group's, so that the passes of a group revisit at most 256 MiB of data (one
 // job if it is larger).  The launches are captured once into a graph; running
-// the batch is one hipGraphLaunch.
+// the batch is one hipGraphLaunch.  The launches of one phase are captured on
+// several streams, so they are independent nodes of the graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,7 +36,7 @@ namespace moma {
 struct BatchLaunch {
   int L;
   bool mul, variant, fw;
-  uint32_t radix_log, threads, grid, nitems;
+  uint32_t phase, radix_log, threads, grid, nitems;
   size_t lds;
   const NttPassArgs* d_passes;
   const void* d_consts;
@@ -73,11 +74,15 @@ struct BatchImpl {
   std::vector<Input> inputs;
   uint64_t items = 0;
   hipStream_t cap = nullptr;
+  std::vector<hipStream_t> side;  // further capture streams: launches of one phase run side by side
+  std::vector<hipEvent_t> events;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~BatchImpl() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipStream_t st : side) (void)hipStreamDestroy(st);
     if (cap) (void)hipStreamDestroy(cap);
     for (void* p : dev_allocs) (void)hipFree(p);
   }
@@ -306,6 +311,7 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
       if (rc) return rc;
       BatchLaunch bl;
       bl.L = L;
+      bl.phase = ph;
       bl.mul = std::get<3>(kv.first);
       bl.variant = std::get<5>(kv.first);
       bl.fw = std::get<6>(kv.first);
@@ -342,19 +348,55 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     b.items += bl.nitems;
   }
   for (const BatchLaunch& bl : b.launches) ntt_batch_prepare(bl.L, bl.radix_log, bl.fw, bl.lds);
-  // capture the launches into one graph
+  // Capture the launches into one graph.  The launches of one phase belong to
+  // different jobs, so they are captured on up to kStreams streams forked from
+  // the capture stream and joined before the next phase: in the graph they are
+  // independent nodes, and one launch's last workgroups can overlap another's.
+  constexpr size_t kStreams = 4;
   if (hipStreamCreate(&b.cap)) return hip_fail(1, "batch stream");
+  size_t widest = 0;  // most launches in one phase
+  {
+    std::map<uint32_t, size_t> per_phase;
+    for (const BatchLaunch& bl : b.launches) widest = std::max(widest, ++per_phase[bl.phase]);
+  }
+  for (size_t k = 1; k < std::min(widest, kStreams); k++) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) return hip_fail(1, "batch stream");
+    b.side.push_back(st);
+  }
+  auto record = [&](hipStream_t st) -> hipEvent_t {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming)) return nullptr;
+    b.events.push_back(e);
+    return hipEventRecord(e, st) ? nullptr : e;
+  };
   if (hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal)) return hip_fail(1, "begin capture");
   int err = 0;
   for (const BlasLaunch& bl : b.blas) {
     err = launch_blas_batch(bl.op, bl.L, bl.variant, bl.fw, bl.d_recs, bl.d_consts, bl.d_items, bl.nitems, b.cap);
     if (err) break;
   }
-  for (const BatchLaunch& bl : b.launches) {
-    if (err) break;
-    err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.variant, bl.fw, bl.threads, bl.lds, bl.grid, bl.d_passes,
-                           bl.d_consts, bl.d_items, bl.nitems, b.cap);
-    if (err) break;
+  for (size_t i = 0; !err && i < b.launches.size();) {
+    size_t j = i;  // launches [i, j) form one phase
+    while (j < b.launches.size() && b.launches[j].phase == b.launches[i].phase) j++;
+    const size_t width = std::min(j - i, 1 + b.side.size());
+    if (width > 1) {
+      hipEvent_t fork = record(b.cap);
+      if (!fork) err = 1;
+      for (size_t k = 0; !err && k + 1 < width; k++)
+        if (hipStreamWaitEvent(b.side[k], fork, 0)) err = 1;
+    }
+    for (size_t k = i; !err && k < j; k++) {
+      const size_t slot = (k - i) % width;
+      const BatchLaunch& bl = b.launches[k];
+      err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.variant, bl.fw, bl.threads, bl.lds, bl.grid,
+                             bl.d_passes, bl.d_consts, bl.d_items, bl.nitems, slot ? b.side[slot - 1] : b.cap);
+    }
+    for (size_t k = 0; !err && k + 1 < width; k++) {
+      hipEvent_t join = record(b.side[k]);
+      if (!join || hipStreamWaitEvent(b.cap, join, 0)) err = 1;
+    }
+    i = j;
   }
   if (!err)
     for (const ZeroFill& z : b.fills) {
