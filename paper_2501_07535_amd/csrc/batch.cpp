@@ -16,8 +16,9 @@
 // of a group share phases, and each group's phases follow the previous
 // group's, so that the passes of a group revisit at most 256 MiB of data (one
 // job if it is larger).  The launches are captured once into a graph; running
-// the batch is one hipGraphLaunch.  The launches of one phase are captured on
-// several streams, so they are independent nodes of the graph.
+// the batch is one hipGraphLaunch.  The launches of different compute limb
+// counts are captured on different streams (a job's passes all have its limb
+// count), so they are independent chains of the graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -348,18 +349,21 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     b.items += bl.nitems;
   }
   for (const BatchLaunch& bl : b.launches) ntt_batch_prepare(bl.L, bl.radix_log, bl.fw, bl.lds);
-  // Capture the launches into one graph.  The launches of one phase belong to
-  // different jobs, so they are captured on up to kStreams streams forked from
-  // the capture stream and joined before the next phase: in the graph they are
-  // independent nodes, and one launch's last workgroups can overlap another's.
+  // Capture the launches into one graph.  All passes of a job have the job's
+  // compute limb count, so each limb count gets one of up to kStreams streams
+  // forked from the capture stream: launch order within a stream keeps every
+  // job's passes in phase order, and the chains of different limb counts are
+  // independent nodes of the graph that run side by side.  The streams join
+  // before the zero fills.
   constexpr size_t kStreams = 4;
   if (hipStreamCreate(&b.cap)) return hip_fail(1, "batch stream");
-  size_t widest = 0;  // most launches in one phase
-  {
-    std::map<uint32_t, size_t> per_phase;
-    for (const BatchLaunch& bl : b.launches) widest = std::max(widest, ++per_phase[bl.phase]);
-  }
-  for (size_t k = 1; k < std::min(widest, kStreams); k++) {
+  std::map<int, size_t> slot_of;  // compute limbs -> stream slot (0: the capture stream)
+  for (const BatchLaunch& bl : b.launches)
+    if (!slot_of.count(bl.L)) {
+      const size_t slot = slot_of.size() % kStreams;
+      slot_of[bl.L] = slot;
+    }
+  for (size_t k = 1; k < std::min(slot_of.size(), kStreams); k++) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) return hip_fail(1, "batch stream");
     b.side.push_back(st);
@@ -376,27 +380,21 @@ static int batch_create(const moma_ntt_job_t* jobs, uint32_t njobs, BatchImpl& b
     err = launch_blas_batch(bl.op, bl.L, bl.variant, bl.fw, bl.d_recs, bl.d_consts, bl.d_items, bl.nitems, b.cap);
     if (err) break;
   }
-  for (size_t i = 0; !err && i < b.launches.size();) {
-    size_t j = i;  // launches [i, j) form one phase
-    while (j < b.launches.size() && b.launches[j].phase == b.launches[i].phase) j++;
-    const size_t width = std::min(j - i, 1 + b.side.size());
-    if (width > 1) {
-      hipEvent_t fork = record(b.cap);
-      if (!fork) err = 1;
-      for (size_t k = 0; !err && k + 1 < width; k++)
-        if (hipStreamWaitEvent(b.side[k], fork, 0)) err = 1;
-    }
-    for (size_t k = i; !err && k < j; k++) {
-      const size_t slot = (k - i) % width;
-      const BatchLaunch& bl = b.launches[k];
-      err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.variant, bl.fw, bl.threads, bl.lds, bl.grid,
-                             bl.d_passes, bl.d_consts, bl.d_items, bl.nitems, slot ? b.side[slot - 1] : b.cap);
-    }
-    for (size_t k = 0; !err && k + 1 < width; k++) {
-      hipEvent_t join = record(b.side[k]);
-      if (!join || hipStreamWaitEvent(b.cap, join, 0)) err = 1;
-    }
-    i = j;
+  if (!err && !b.side.empty()) {
+    hipEvent_t fork = record(b.cap);
+    if (!fork) err = 1;
+    for (size_t k = 0; !err && k < b.side.size(); k++)
+      if (hipStreamWaitEvent(b.side[k], fork, 0)) err = 1;
+  }
+  for (size_t k = 0; !err && k < b.launches.size(); k++) {
+    const BatchLaunch& bl = b.launches[k];
+    const size_t slot = slot_of[bl.L];
+    err = launch_ntt_batch(bl.L, bl.radix_log, bl.mul, bl.variant, bl.fw, bl.threads, bl.lds, bl.grid, bl.d_passes,
+                           bl.d_consts, bl.d_items, bl.nitems, slot ? b.side[slot - 1] : b.cap);
+  }
+  for (size_t k = 0; !err && k < b.side.size(); k++) {
+    hipEvent_t join = record(b.side[k]);
+    if (!join || hipStreamWaitEvent(b.cap, join, 0)) err = 1;
   }
   if (!err)
     for (const ZeroFill& z : b.fills) {
