@@ -14,11 +14,12 @@
 // another in stream order, which is the only dependency between a job's
 // passes.  Jobs whose data is 16 MiB or more run in groups instead: the jobs
 // of a group share phases, and each group's phases follow the previous
-// group's, so that the passes of a group revisit at most 256 MiB of data (one
-// job if it is larger).  The launches are captured once into a graph; running
-// the batch is one hipGraphLaunch.  The launches of different compute limb
-// counts are captured on different streams (a job's passes all have its limb
-// count), so they are independent chains of the graph.
+// group's, so that the passes of a group of one limb count revisit at most
+// 256 MiB of data (one job if it is larger).  The launches are captured once
+// into a graph; running the batch is one hipGraphLaunch.  The launches of
+// different compute limb counts are captured on different streams (a job's
+// passes all have its limb count), so they are independent chains of the
+// graph, and groups of different limb counts may run side by side.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
