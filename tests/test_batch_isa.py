@@ -4,11 +4,11 @@ the data and twiddles with global (not flat) loads and stores, as the plain
 pass kernel does with addresses passed as kernel arguments.  A flat access
 also counts on the LDS wait counter, so each LDS wait of a round would wait
 for the HBM loads in flight too."""
+import importlib.util
 import os
 import re
 import shutil
 import subprocess
-import sys
 
 import pytest
 
@@ -40,8 +40,9 @@ def _kernels(asm: str) -> dict:
 
 @pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc is not available")
 def test_batch_kernels_use_global_memory_instructions(tmp_path):
-    sys.path.insert(0, os.path.join(ROOT, "paper_2501_07535_amd"))
-    import build
+    spec = importlib.util.spec_from_file_location("moma_build_script", os.path.join(ROOT, "paper_2501_07535_amd", "build.py"))
+    build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(build)
     src = tmp_path / "batch_isa.hip"
     src.write_text(SRC)
     asm = tmp_path / "batch_isa.s"
